@@ -1,0 +1,194 @@
+"""Pins of the oracle's integrator, thermostat, noise and observables.
+
+* energy conservation and time reversal of velocity Verlet without thermostat;
+* the exact momentum bookkeeping of the Lees-Edwards velocity jump;
+* the Philox4x32-10 generator against ROCm's rocRAND engine run on the host;
+* thermostat statistics of an ideal gas, with and without shear, against the
+  stationary moments of the Langevin equation on the peculiar velocity (which
+  also fixes the kinetic part of the stress and the linear flow profile).
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2109_11083_amd import inputs
+
+
+def _lj_c1(shear_rate=0.0, gamma=1.0, kT=1.0, seed=11, **kw):
+    w = inputs.lj_workload(n_side=10, shear_rate=shear_rate, kT=kT, seed=seed)
+    p = O.make_params(w.x.shape[1], w.box, shear_rate=shear_rate, gamma=gamma, kT=kT, seed=seed, **kw)
+    return w, p
+
+
+def _total_energy(sim):
+    _, _, epot = sim.conservative()
+    ekin = 0.5 * sim.p.mass * (sim.u ** 2).sum()
+    return epot + ekin
+
+
+@pytest.mark.slow
+def test_nve_energy_drift_small():
+    w, p = _lj_c1(shear_rate=0.0, gamma=0.0, lj_shift=O.lj_energy_shift(2.5))
+    sim = O.Sim(w.x, w.u, p)
+    e0 = _total_energy(sim)
+    es = []
+    for _ in range(10):
+        sim.run(100)
+        es.append(_total_energy(sim))
+    es = np.array(es)
+    # truncated-force dynamics: small drift per particle over 1000 steps
+    assert np.abs(es - e0).max() / w.x.shape[1] < 2e-3
+
+
+def test_time_reversal_without_thermostat():
+    w, p = _lj_c1(shear_rate=0.0, gamma=0.0)
+    sim = O.Sim(w.x, w.u, p)
+    x0 = sim.x.copy()
+    sim.run(60)
+    sim.u = -sim.u
+    # F of the current state is the conservative force (no thermostat), still valid
+    sim.run(60)
+    d = sim.x - x0
+    d -= np.array(w.box)[:, None] * np.round(d / np.array(w.box)[:, None])
+    assert np.abs(d).max() < 1e-8
+
+
+def test_momentum_bookkeeping_of_velocity_jump():
+    """Without thermostat, pair forces conserve momentum, so the lab momentum
+    changes only through the velocity jump at the gradient faces: each upward
+    crossing removes m*shear_rate*L_y from P_x and each downward crossing adds it."""
+    sr = 0.5
+    w, p = _lj_c1(shear_rate=sr, gamma=0.0)
+    n = w.x.shape[1]
+    L = w.box[1]
+    sim = O.Sim(w.x, w.u, p)
+    P0 = sim.u.sum(axis=1)
+    ups = downs = 0
+    for _ in range(200):
+        y0 = sim.x[1].copy()
+        sim.run(1)
+        dy = sim.x[1] - y0
+        ups += int((dy < -L / 2).sum())
+        downs += int((dy > L / 2).sum())
+    P = sim.u.sum(axis=1)
+    assert ups + downs > 5
+    assert abs(P[1] - P0[1]) < 1e-9
+    assert abs(P[2] - P0[2]) < 1e-9
+    assert P[0] - P0[0] == pytest.approx(-sr * L * (ups - downs), abs=1e-8)
+
+
+# --------------------------------------------------------------- Philox
+_HELPER_SRC = os.path.join(os.path.dirname(__file__), "helpers", "rocrand_philox_host.cpp")
+
+
+@pytest.fixture(scope="module")
+def rocrand_host(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("ROCm rocRAND headers not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rph")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, _HELPER_SRC])
+    return exe
+
+
+def test_philox_matches_rocrand_engine(rocrand_host):
+    cases = [(0, 0, 0), (11, 0, 1), (0x1234567890ABCDEF, 77, 5), (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 40 + 3),
+             (42, 999999, 123456789)]
+    for seed, tag, step in cases:
+        out = subprocess.check_output([rocrand_host, str(seed), str(tag), str(step)]).split()
+        ref = [int(v) for v in out]
+        ctr = [step & 0xFFFFFFFF, step >> 32, tag & 0xFFFFFFFF, tag >> 32]
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        assert O.philox(ctr, key) == ref, (seed, tag, step)
+
+
+def test_noise_uniform_moments():
+    th = np.array([O.noise(7, s, t) for s in range(200) for t in range(100)])
+    assert np.all(np.abs(th) < 0.5)
+    assert abs(th.mean()) < 0.004
+    assert th.var() == pytest.approx(1.0 / 12.0, rel=0.02)
+    c = np.corrcoef(th.T)
+    assert np.abs(c - np.eye(3)).max() < 0.02
+
+
+# ---------------------------------------------- thermostat / ideal-gas physics
+def _ideal_gas(shear_rate, gamma, kT, n=600, L=9.0, seed=5):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, L, size=(3, n))
+    c = inputs.maxwell(n, kT, 1.0, seed + 1)
+    u = inputs.streaming_initial_velocity(x, c, shear_rate, L)
+    # eps = 0 switches the pair force off; a short cutoff keeps the pair search cheap
+    p = O.make_params(n, (L, L, L), shear_rate=shear_rate, gamma=gamma, kT=kT, eps=0.0, rc=0.5,
+                      seed=seed, dt=0.005)
+    return O.Sim(x, u, p), p
+
+
+@pytest.mark.slow
+def test_ideal_gas_equipartition_and_sheared_moments():
+    """For dc/dt = -gamma c - shear_rate c_y e_x + noise (the Langevin force on
+    the peculiar velocity, Eq. langevin, in the sheared frame) the stationary
+    moments are <c_y^2> = kT/m, <c_x c_y> = -shear_rate kT / (2 gamma m),
+    <c_x^2> = kT/m (1 + shear_rate^2 / (2 gamma^2)).  The kinetic stress is
+    then sigma_xy = rho shear_rate kT / (2 gamma), and <u_x(y)> is the linear
+    profile shear_rate (y - L_y/2)."""
+    sr, gamma, kT = 0.8, 1.0, 1.0
+    sim, p = _ideal_gas(sr, gamma, kT)
+    n = sim.n
+    L = sim.p.box[1]
+    sim.run(400)
+    sxy, cxx, cyy, prof_c, prof_u = [], [], [], np.zeros(10), np.zeros(10)
+    for _ in range(120):
+        s = sim.run(40, sample_every=40)
+        sxy.append(s[0, 3])
+        cx = sim.u[0] - sr * (sim.x[1] - L / 2)
+        cxx.append((cx ** 2).mean())
+        cyy.append((sim.u[1] ** 2).mean())
+        ob = O.observables(sim.x, sim.u, sim.Delta, sim.p, nbins=10)
+        prof_c += ob["count"]
+        prof_u += ob["sum_ux"]
+    rho = n / L ** 3
+    assert np.mean(cyy) == pytest.approx(kT, rel=0.04)
+    assert np.mean(cxx) == pytest.approx(kT * (1 + sr ** 2 / (2 * gamma ** 2)), rel=0.05)
+    assert np.mean(sxy) == pytest.approx(rho * sr * kT / (2 * gamma), rel=0.08)
+    centres = (np.arange(10) + 0.5) / 10 * L
+    vx = prof_u / prof_c
+    slope = np.polyfit(centres, vx, 1)[0]
+    assert slope == pytest.approx(sr, rel=0.05)
+    assert prof_c.min() > 0.8 * prof_c.mean()
+
+
+def test_ideal_gas_no_shear_equipartition():
+    sim, p = _ideal_gas(0.0, 2.0, 1.5, n=400)
+    sim.run(300)
+    ks = []
+    for _ in range(60):
+        sim.run(20)
+        ks.append(O.observables(sim.x, sim.u, sim.Delta, sim.p)["kT"])
+    assert np.mean(ks) == pytest.approx(1.5, rel=0.03)
+
+
+@pytest.mark.slow
+def test_lj_shear_linear_profile_flat_density():
+    """LJ fluid under shear with the Langevin force on the peculiar velocity:
+    linear v_x(y) with slope shear_rate and no density layering (Section 3.1)."""
+    sr = 0.5
+    w, p = _lj_c1(shear_rate=sr, gamma=1.0, kT=1.0)
+    sim = O.Sim(w.x, w.u, p)
+    sim.run(300)
+    nb = 10
+    cnt, sux = np.zeros(nb), np.zeros(nb)
+    for _ in range(30):
+        sim.run(20)
+        ob = O.observables(sim.x, sim.u, sim.Delta, sim.p, nbins=nb)
+        cnt += ob["count"]; sux += ob["sum_ux"]
+    L = w.box[1]
+    centres = (np.arange(nb) + 0.5) / nb * L
+    slope, icpt = np.polyfit(centres, sux / cnt, 1)
+    assert slope == pytest.approx(sr, rel=0.1)
+    assert abs(icpt + sr * L / 2) < 0.2
+    assert cnt.max() / cnt.mean() < 1.15 and cnt.min() / cnt.mean() > 0.85
