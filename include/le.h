@@ -1,0 +1,189 @@
+/*
+ * le.h -- C ABI of the MI355X Lees-Edwards shear-flow MD hot path.
+ *
+ * Method: Xu, Vance, Tretyakov, Stuehn, Brinkmann, "Implementation and
+ * Parallel Optimization of the Lees-Edwards Boundary Condition in
+ * ESPResSo++", arXiv 2109.11083.  One call advances a sheared periodic box
+ * of N particles: Lees-Edwards cell build (Section 2.3, Fig. decomp),
+ * LJ/WCA pair forces (Eqs. lj, lj-shift) and Kremer-Grest FENE bonds
+ * (Eq. fene), velocity Verlet with the boundary crossing of Eq. pos_new, a
+ * Langevin force on the peculiar velocity (Eqs. vi, langevin) driven by
+ * counter-based Philox4x32-10 noise, and the Irving-Kirkwood stress that
+ * yields the viscosity (Eqs. tensor, viscosity).
+ *
+ * Axes: x is the flow direction, y the gradient direction (the paper's z),
+ * z the vorticity direction.  The periodic image directly above the box
+ * (y + L_y) is displaced by +Delta along x, Delta = shear_rate * L_y * t
+ * reduced into [0, L_x); a particle leaving through y = L_y re-enters at
+ * y - L_y with x - Delta and lab velocity u_x - shear_rate * L_y.
+ *
+ * Units are reduced (epsilon = sigma = m = k_B = 1 in the paper's runs).
+ *
+ * Memory and ownership
+ *   - Every array argument is a DEVICE pointer unless stated otherwise.
+ *   - Particle arrays at the ABI are float64 structure-of-arrays [3][n]
+ *     (all x, then all y, then all z), indexed by particle tag 0..n-1.
+ *   - The caller owns all device memory, including ONE workspace buffer of at
+ *     least le_workspace_bytes() bytes, which must stay allocated and
+ *     untouched until le_destroy().  The library never calls hipMalloc or
+ *     hipFree; it allocates only its small host-side handle.
+ *   - Inputs given to le_init() are copied; the caller may free them after.
+ *
+ * Streams and synchronisation
+ *   - All work is enqueued on the hipStream_t passed to le_init() and is
+ *     asynchronous, except le_build_cells() (it returns a pair count to the
+ *     host), le_get_state() and le_sync(), which wait for the stream.
+ *
+ * Errors
+ *   - Invalid arguments, geometry and workspace size are reported
+ *     synchronously by the call that receives them.
+ *   - Errors found on the device (a FENE bond stretched to r >= R0, a
+ *     non-finite coordinate, a neighbour-list or cell overflow) are latched
+ *     in a status word inside the workspace.  Every later kernel of that
+ *     simulation becomes a no-op, and the next synchronising call returns
+ *     the status.  le_step() returns a latched status once a synchronising
+ *     call has seen it.  Only le_destroy() and a new le_init() clear it.
+ *   - No call throws; le_strerror() maps a status to a static string.
+ *
+ * Calls on one le_sim are not thread-safe; distinct le_sim handles are
+ * independent (they may share a stream).
+ */
+#ifndef LE_H
+#define LE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct le_sim le_sim;
+typedef int32_t le_status;
+
+#define LE_OK 0
+#define LE_E_ARG (-1)       /* bad argument (null pointer, n < 2, dt <= 0, ...)    */
+#define LE_E_GEOMETRY (-2)  /* box too small: L_a <= 2 r_list or < 3 cells on an axis */
+#define LE_E_WORKSPACE (-3) /* workspace smaller than le_workspace_bytes()          */
+#define LE_E_BOND (-4)      /* FENE bond reached r >= R0 (Eq. fene: V = +infinity)  */
+#define LE_E_NONFINITE (-5) /* NaN or Inf in positions or velocities                */
+#define LE_E_CAPACITY (-6)  /* neighbour list or cell occupancy over capacity       */
+#define LE_E_HIP (-7)       /* a HIP runtime call failed                            */
+#define LE_E_STATE (-8)     /* call not valid in the current state                  */
+
+#define LE_PAIR_LJ 0  /* 4 eps[(s/r)^12 - (s/r)^6], force truncated at rc (Eq. lj) */
+#define LE_PAIR_WCA 1 /* the same force with rc = 2^(1/6) s (Eq. lj-shift)         */
+
+#define LE_FP64 0  /* every operation in float64                                    */
+#define LE_MIXED 1 /* pair-force arithmetic in float32 after a float64 cutoff test;
+                      positions, offset, bonds, sums and integrator in float64      */
+
+/* Parameters of one simulation (Sections 2.1, 2.2, 2.4).  All 8-byte fields
+ * come first so that the layout has no padding. */
+typedef struct le_params {
+  int64_t n;           /* number of particles (>= 2)                               */
+  double box[3];       /* L_x, L_y, L_z                                             */
+  double shear_rate;   /* gamma_dot of Eq. shear-rate (any sign; 0 = equilibrium)   */
+  double dt;           /* time step (> 0)                                           */
+  double kT;           /* thermostat temperature (>= 0)                             */
+  double gamma;        /* Langevin friction xi of Eq. langevin (>= 0; 0 = NVE)      */
+  double mass;         /* particle mass (> 0)                                       */
+  double eps, sigma;   /* pair parameters                                           */
+  double rc;           /* pair cutoff; pairs interact iff r < rc                    */
+  double skin;         /* Verlet skin (>= 0); 0 rebuilds and wraps every step       */
+  double fene_k;       /* FENE spring constant k                                    */
+  double fene_r0;      /* FENE maximal bond length R0                               */
+  int64_t n_chains;    /* linear chains: tag = chain*chain_len + k; 0 = no bonds    */
+  uint64_t seed;       /* Philox key of the thermostat noise                        */
+  int32_t chain_len;   /* beads per chain (0 = no bonds)                            */
+  int32_t pair;        /* LE_PAIR_LJ or LE_PAIR_WCA                                 */
+  int32_t precision;   /* LE_FP64 or LE_MIXED                                       */
+  int32_t cells[3];    /* cell grid; 0 = floor(L_a / (rc + skin)); each must be >= 3 */
+  int32_t max_neighbors; /* neighbour-list capacity per particle; 0 = from density  */
+  int32_t tune;        /* launch-shape selector (0 = default); results do not depend on it */
+} le_params;
+
+/* Device bytes needed for a simulation with these parameters.  Pure host
+ * function; validates the parameters (same errors as le_init). */
+le_status le_workspace_bytes(const le_params* p, size_t* bytes);
+
+/* Create a simulation from the state (x0, u0) at step index step0.
+ * x0, u0: device float64 [3][n] by tag; positions may lie outside the box
+ * (they are wrapped with the offset of step0, Eq. pos_new), u0 are lab-frame
+ * velocities.  The force of step step0 (conservative + Langevin with the
+ * noise of step0) is computed before returning.  workspace: device buffer of
+ * ws_bytes >= le_workspace_bytes(p).  hip_stream: a hipStream_t (NULL = the
+ * null stream).  *out receives the handle. */
+le_status le_init(const le_params* p, const double* x0, const double* u0, void* workspace,
+                  size_t ws_bytes, void* hip_stream, int64_t step0, le_sim** out);
+
+/* Rebuild now: apply the boundary crossing and periodic wrap to the current
+ * state, re-bin the particles into cells (Section 2.3: ids
+ * (iz*ny + iy)*nx + ix, order ascending (cell, tag)), recompute the
+ * Lees-Edwards cell stencil (neighbour rows across the gradient faces offset
+ * by Delta, Fig. decomp) and the neighbour lists of radius rc + skin.
+ * Optional device outputs (NULL to skip):
+ *   cell_of[n]  int32 cell id of each tag;
+ *   order[n]    int32 tag at each cell-sorted slot;
+ *   pairs       int64 [pairs_cap][2]: every unordered pair (tag_i < tag_j)
+ *               with r < rc + skin, in unspecified order; *n_pairs (host)
+ *               receives the total count even when it exceeds pairs_cap.
+ * Synchronous when n_pairs is given. */
+le_status le_build_cells(le_sim* s, int32_t* cell_of, int32_t* order, int64_t* pairs,
+                         int64_t pairs_cap, int64_t* n_pairs);
+
+/* Conservative forces of the current state (Eqs. lj/lj-shift + fene).
+ * f_out: device float64 [3][n] by tag (may be NULL); virial6: device
+ * float64[6] receiving W_ab = sum over pairs i<j of d_a F_ij,b in the order
+ * xx, yy, zz, xy, xz, yz (may be NULL).  Does not change the state. */
+le_status le_forces(le_sim* s, double* f_out, double* virial6);
+
+/* Advance nsteps velocity-Verlet steps (Section 2.2).  When sample_every > 0,
+ * the stress tensor (see le_stress) of every sample_every-th new state is
+ * written to stress_ring[(k mod ring_cap)][6], k = 0, 1, ... counted within
+ * this call; stress_ring is a device float64 buffer of ring_cap*6 values. */
+le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
+                  int64_t ring_cap);
+
+/* Stress of the current state (Eq. tensor): sigma_ab = -(1/V)[sum_i m c_a c_b
+ * + sum_{i<j} d_a F_ij,b] with peculiar velocities c (Eq. vi) and
+ * conservative forces only; order xx, yy, zz, xy, xz, yz.  The viscosity of
+ * Eq. viscosity is <sigma_xy> / shear_rate.  sigma6: device float64[6]. */
+le_status le_stress(le_sim* s, double* sigma6);
+
+/* Copy the current state out in tag order (device float64 [3][n] each; either
+ * may be NULL) and its step index (*step, host, may be NULL).  Waits for the
+ * stream and returns any latched device error. */
+le_status le_get_state(le_sim* s, double* x, double* u, int64_t* step);
+
+/* Wait for all enqueued work of the simulation; returns any latched error. */
+le_status le_sync(le_sim* s);
+
+/* Telemetry (host outputs, synchronous): neighbour-list rebuilds since
+ * le_init and the largest neighbour count seen at the last rebuild. */
+le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors);
+
+/* Release the handle.  The workspace is the caller's and is not touched. */
+le_status le_destroy(le_sim* s);
+
+/* Static description of a status code. */
+const char* le_strerror(le_status st);
+
+/* Lees-Edwards offsets Delta_k for k = step0 .. step0+count-1 as the device
+ * computes them (Eq. pos_new; fmod of shear_rate*L_y*(k*dt) by L_x, folded
+ * into [0, L_x)).  out: device float64[count].  Enqueued on hip_stream. */
+le_status le_offsets(double shear_rate, double Lx, double Ly, double dt, int64_t step0,
+                     int64_t count, double* out, void* hip_stream);
+
+/* Philox4x32-10 blocks as the thermostat draws them: for each k, counter
+ * ctr[4k..4k+3] and key key[2k..2k+1] (device uint32) give out[4k..4k+3]
+ * (device uint32).  The thermostat of step s uses counter (s lo, s hi, tag,
+ * 0) and key (seed lo, seed hi); word a maps to (r_a + 1/2) 2^-32 - 1/2. */
+le_status le_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                    void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LE_H */

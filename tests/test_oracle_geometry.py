@@ -231,3 +231,16 @@ def test_cells_are_geometric_and_order_sorted():
     assert np.all(np.diff(keys) > 0)
     assert sorted(order.tolist()) == list(range(500))
     assert cell_of[1] == nc[0] * nc[1] * nc[2] - 1
+
+
+def test_cell_index_clamped_when_product_rounds_up():
+    """x one ulp below L_x with x * (n/L_x) rounding up to n must land in the
+    last cell, never in a cell n that does not exist."""
+    L = float.fromhex("0x1.7db3795860d14p+5")
+    x = float.fromhex("0x1.7db3795860d13p+5")
+    nc = (12, 12, 12)
+    assert int(x * (12 / L)) == 12  # the rounding this case is about
+    pos = np.array([[x, 1.0], [x, 1.0], [x, 1.0]])
+    cell_of, order = O.cells(pos, nc, (L, L, L))
+    assert cell_of[0] == 12 ** 3 - 1
+    assert cell_of[1] == 0
