@@ -110,12 +110,14 @@ le_status le_workspace_bytes(const le_params* p, size_t* bytes);
 /* Create a simulation from the state (x0, u0) at step index step0.
  * x0, u0: device float64 [3][n] by tag; positions may lie outside the box
  * (they are wrapped with the offset of step0, Eq. pos_new), u0 are lab-frame
- * velocities.  The force of step step0 (conservative + Langevin with the
- * noise of step0) is computed before returning.  workspace: device buffer of
- * ws_bytes >= le_workspace_bytes(p).  hip_stream: a hipStream_t (NULL = the
- * null stream).  *out receives the handle. */
-le_status le_init(const le_params* p, const double* x0, const double* u0, void* workspace,
-                  size_t ws_bytes, void* hip_stream, int64_t step0, le_sim** out);
+ * velocities.  f0: NULL, or the device float64 [3][n] total force of step
+ * step0 as returned by le_get_state (exact restart); when NULL the force of
+ * step0 (conservative + Langevin with the noise of step0, evaluated at u0) is
+ * computed here.  workspace: device buffer of ws_bytes >=
+ * le_workspace_bytes(p).  hip_stream: a hipStream_t (NULL = the null
+ * stream).  *out receives the handle. */
+le_status le_init(const le_params* p, const double* x0, const double* u0, const double* f0,
+                  void* workspace, size_t ws_bytes, void* hip_stream, int64_t step0, le_sim** out);
 
 /* Rebuild now: apply the boundary crossing and periodic wrap to the current
  * state, re-bin the particles into cells (Section 2.3: ids
@@ -151,10 +153,14 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
  * Eq. viscosity is <sigma_xy> / shear_rate.  sigma6: device float64[6]. */
 le_status le_stress(le_sim* s, double* sigma6);
 
-/* Copy the current state out in tag order (device float64 [3][n] each; either
- * may be NULL) and its step index (*step, host, may be NULL).  Waits for the
- * stream and returns any latched device error. */
-le_status le_get_state(le_sim* s, double* x, double* u, int64_t* step);
+/* Copy the current state out in tag order: positions x, lab velocities u and
+ * the total force f of the current step (device float64 [3][n] each; any may
+ * be NULL), and its step index (*step, host, may be NULL).  Pending boundary
+ * crossings are applied first (a rebuild, which changes no physical
+ * quantity), so the positions lie in the box; le_init(x, u, f, step) then
+ * continues the run exactly.  Waits for the stream and returns any latched
+ * device error. */
+le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step);
 
 /* Wait for all enqueued work of the simulation; returns any latched error. */
 le_status le_sync(le_sim* s);

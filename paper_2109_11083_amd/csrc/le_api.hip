@@ -1,0 +1,351 @@
+// le_api.hip -- host side of the C ABI declared in include/le.h: parameter
+// validation, workspace carving, and the launch sequence of each entry point.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "le_internal.h"
+
+using namespace le;
+
+struct le_sim {
+  le_params p;
+  Dev d;
+  hipStream_t stream;
+  int32_t host_status;                 // last status seen by a synchronising call
+  unsigned long long* counter;         // device scratch counter (pairs_out)
+  double* scratch6;                    // device 6 doubles
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Geometry {
+  int32_t nc[3];
+  double rc, rlist;
+  int32_t K;
+  int64_t np;
+  int32_t nblocks;
+};
+
+le_status validate(const le_params* p, Geometry* g) {
+  if (!p) return LE_E_ARG;
+  if (p->n < 2 || p->n > (int64_t)0x7fffffff / 4) return LE_E_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (!(p->box[a] > 0.0) || !isfinite(p->box[a])) return LE_E_ARG;
+  if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->kT >= 0.0) || !(p->gamma >= 0.0)) return LE_E_ARG;
+  if (!isfinite(p->shear_rate) || !(p->sigma > 0.0) || !(p->skin >= 0.0) || !isfinite(p->eps))
+    return LE_E_ARG;
+  if (p->pair != LE_PAIR_LJ && p->pair != LE_PAIR_WCA) return LE_E_ARG;
+  if (p->precision != LE_FP64 && p->precision != LE_MIXED) return LE_E_ARG;
+  double rc = p->rc;
+  if (rc <= 0.0) rc = (p->pair == LE_PAIR_WCA) ? pow(2.0, 1.0 / 6.0) * p->sigma : 2.5 * p->sigma;
+  if (p->chain_len < 0 || p->n_chains < 0) return LE_E_ARG;
+  if (p->n_chains > 0) {
+    if (p->chain_len < 2 || p->n_chains * (int64_t)p->chain_len > p->n) return LE_E_ARG;
+    if (!(p->fene_r0 > 0.0) || !(p->fene_k >= 0.0)) return LE_E_ARG;
+  }
+  double rlist = rc + p->skin;
+  for (int a = 0; a < 3; ++a) {
+    int32_t k = p->cells[a];
+    if (k <= 0) k = (int32_t)floor(p->box[a] / (rlist * (1.0 + 1e-9)));
+    if (k < 3) return LE_E_GEOMETRY;
+    if (p->box[a] / k < rlist) return LE_E_GEOMETRY;
+    if ((int64_t)k * k * k > (int64_t)1 << 30) return LE_E_GEOMETRY;
+    g->nc[a] = k;
+  }
+  if ((int64_t)g->nc[0] * g->nc[1] * g->nc[2] > (int64_t)0x7fffffff - 1) return LE_E_GEOMETRY;
+  g->rc = rc;
+  g->rlist = rlist;
+  if (p->max_neighbors > 0) {
+    g->K = p->max_neighbors;
+  } else {
+    double rho = (double)p->n / (p->box[0] * p->box[1] * p->box[2]);
+    double mean = 4.0 / 3.0 * M_PI * rlist * rlist * rlist * rho;
+    g->K = (int32_t)ceil(2.0 * mean) + 32;
+  }
+  if (g->K > 4096) g->K = 4096;
+  g->np = (p->n + kBlock - 1) / kBlock * kBlock;
+  g->nblocks = (int32_t)(g->np / kBlock);
+  return LE_OK;
+}
+
+// Carve the workspace; with base == nullptr only the size is computed.
+size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* s) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* r = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return r;
+  };
+  const size_t np = (size_t)g.np;
+  const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+  const size_t nchunks = (ncell + kScanChunk - 1) / kScanChunk;
+  Dev t;
+  memset(&t, 0, sizeof(t));
+  t.ctrl = (Ctrl*)take(sizeof(Ctrl));
+  for (int b = 0; b < 2; ++b) {
+    t.pos[b] = (double*)take(4 * np * sizeof(double));
+    t.vel[b] = (double*)take(3 * np * sizeof(double));
+    t.frc[b] = (double*)take(3 * np * sizeof(double));
+    t.tag[b] = (int32_t*)take(np * sizeof(int32_t));
+  }
+  t.slot_of_tag = (int32_t*)take(np * sizeof(int32_t));
+  t.cell_of = (int32_t*)take(np * sizeof(int32_t));
+  t.rank = (int32_t*)take(np * sizeof(int32_t));
+  t.src = (int32_t*)take(np * sizeof(int32_t));
+  t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
+  t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
+  t.block_sums = (int32_t*)take(nchunks * sizeof(int32_t));
+  t.nl = (int32_t*)take((size_t)g.K * np * sizeof(int32_t));
+  t.nlc = (uint8_t*)take((size_t)g.K * np);
+  t.n_plain = (int32_t*)take(np * sizeof(int32_t));
+  t.n_img = (int32_t*)take(np * sizeof(int32_t));
+  t.bond = (p->chain_len > 0) ? (int32_t*)take(2 * np * sizeof(int32_t)) : nullptr;
+  t.partials = (double*)take((size_t)g.nblocks * kStressComps * sizeof(double));
+  unsigned long long* counter = (unsigned long long*)take(sizeof(unsigned long long));
+  double* scratch6 = (double*)take(6 * sizeof(double));
+  if (d) {
+    // copy buffer pointers into d (geometry fields are filled by the caller)
+    d->ctrl = t.ctrl;
+    for (int b = 0; b < 2; ++b) {
+      d->pos[b] = t.pos[b]; d->vel[b] = t.vel[b]; d->frc[b] = t.frc[b]; d->tag[b] = t.tag[b];
+    }
+    d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->src = t.src;
+    d->cell_count = t.cell_count; d->cell_start = t.cell_start; d->block_sums = t.block_sums;
+    d->nl = t.nl; d->nlc = t.nlc; d->n_plain = t.n_plain; d->n_img = t.n_img; d->bond = t.bond;
+    d->partials = t.partials;
+  }
+  if (s) { s->counter = counter; s->scratch6 = scratch6; }
+  return off + kAlign;  // room to align the caller's base pointer
+}
+
+void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
+  d->Lx = p->box[0]; d->Ly = p->box[1]; d->Lz = p->box[2];
+  d->nx = g.nc[0]; d->ny = g.nc[1]; d->nz = g.nc[2];
+  d->ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  d->inv_lx = (double)g.nc[0] / p->box[0];
+  d->inv_ly = (double)g.nc[1] / p->box[1];
+  d->inv_lz = (double)g.nc[2] / p->box[2];
+  d->lx = p->box[0] / (double)g.nc[0];
+  d->shear_rate = p->shear_rate;
+  d->sv = p->shear_rate * p->box[1];
+  d->dt = p->dt;
+  d->h = 0.5 * p->dt / p->mass;
+  d->gamma_m = p->gamma * p->mass;
+  d->pref = sqrt(24.0 * p->gamma * p->mass * p->kT / p->dt);
+  d->mass = p->mass;
+  d->eps24 = 24.0 * p->eps;
+  d->sig2 = p->sigma * p->sigma;
+  d->rc2 = g.rc * g.rc;
+  d->rlist = g.rlist;
+  d->rlist2 = g.rlist * g.rlist;
+  d->fene_k = p->fene_k;
+  d->fene_r02 = p->fene_r0 * p->fene_r0;
+  d->inv_vol = 1.0 / (p->box[0] * p->box[1] * p->box[2]);
+  d->n = (int32_t)p->n;
+  d->np = (int32_t)g.np;
+  d->K = g.K;
+  d->chain_len = p->n_chains > 0 ? p->chain_len : 0;
+  d->n_bonded = (int32_t)(p->n_chains * (int64_t)p->chain_len);
+  d->precision = p->precision;
+  d->seed_lo = (uint32_t)p->seed;
+  d->seed_hi = (uint32_t)(p->seed >> 32);
+  d->nblocks = g.nblocks;
+}
+
+le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
+
+le_status read_status(le_sim* s) {
+  int32_t st = 0;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LE_E_HIP;
+  if (hipMemcpy(&st, &s->d.ctrl->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return LE_E_HIP;
+  if (st != 0) s->host_status = st;
+  return s->host_status;
+}
+
+}  // namespace
+
+extern "C" {
+
+le_status le_workspace_bytes(const le_params* p, size_t* bytes) {
+  if (!bytes) return LE_E_ARG;
+  Geometry g;
+  le_status st = validate(p, &g);
+  if (st != LE_OK) return st;
+  *bytes = carve(p, g, nullptr, nullptr, nullptr);
+  return LE_OK;
+}
+
+le_status le_init(const le_params* p, const double* x0, const double* u0, const double* f0,
+                  void* workspace, size_t ws_bytes, void* hip_stream, int64_t step0, le_sim** out) {
+  if (!out || !x0 || !u0 || !workspace) return LE_E_ARG;
+  *out = nullptr;
+  Geometry g;
+  le_status st = validate(p, &g);
+  if (st != LE_OK) return st;
+  size_t need = carve(p, g, nullptr, nullptr, nullptr);
+  if (ws_bytes < need) return LE_E_WORKSPACE;
+  le_sim* s = new (std::nothrow) le_sim;
+  if (!s) return LE_E_ARG;
+  memset(s, 0, sizeof(*s));
+  s->p = *p;
+  s->p.rc = g.rc;
+  s->stream = (hipStream_t)hip_stream;
+  char* base = (char*)(((uintptr_t)workspace + kAlign - 1) / kAlign * kAlign);
+  carve(p, g, base, &s->d, s);
+  fill_geometry(p, g, &s->d);
+  double Delta0 = le_offset(step0, p->dt, s->d.sv, p->box[0]);
+  st = hip_check(launch_load_state(s->d, s->stream, x0, u0, f0, step0, Delta0));
+  if (st == LE_OK) st = hip_check(launch_rebuild(s->d, s->stream, true));
+  if (st == LE_OK && !f0) st = hip_check(launch_force(s->d, s->stream, kInitForce, false, nullptr, nullptr));
+  if (st != LE_OK) {
+    delete s;
+    return st;
+  }
+  *out = s;
+  return LE_OK;
+}
+
+le_status le_build_cells(le_sim* s, int32_t* cell_of, int32_t* order, int64_t* pairs,
+                         int64_t pairs_cap, int64_t* n_pairs) {
+  if (!s) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  le_status st = hip_check(launch_rebuild(s->d, s->stream, true));
+  if (st == LE_OK && (cell_of || order))
+    st = hip_check(launch_state_out(s->d, s->stream, nullptr, nullptr, cell_of, order));
+  if (st == LE_OK && (pairs || n_pairs)) {
+    st = hip_check(hipMemsetAsync(s->counter, 0, sizeof(unsigned long long), s->stream));
+    if (st == LE_OK)
+      st = hip_check(launch_pairs_out(s->d, s->stream, pairs, pairs ? pairs_cap : 0, s->counter));
+    if (st == LE_OK && n_pairs) {
+      unsigned long long cnt = 0;
+      st = read_status(s);
+      if (st == LE_OK && hipMemcpy(&cnt, s->counter, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+        st = LE_E_HIP;
+      *n_pairs = (int64_t)cnt;
+    }
+  }
+  return st;
+}
+
+le_status le_forces(le_sim* s, double* f_out, double* virial6) {
+  if (!s) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  le_status st = hip_check(launch_force(s->d, s->stream, kForcesOnly, false, f_out, nullptr));
+  if (st == LE_OK && virial6) st = hip_check(launch_stress_final(s->d, s->stream, virial6, true));
+  return st;
+}
+
+le_status le_stress(le_sim* s, double* sigma6) {
+  if (!s || !sigma6) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  le_status st = hip_check(launch_force(s->d, s->stream, kForcesOnly, false, nullptr, nullptr));
+  if (st == LE_OK) st = hip_check(launch_stress_final(s->d, s->stream, sigma6, false));
+  return st;
+}
+
+le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
+                  int64_t ring_cap) {
+  if (!s || nsteps < 0) return LE_E_ARG;
+  if (sample_every > 0 && (!stress_ring || ring_cap <= 0)) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  if (nsteps == 0) return LE_OK;
+  const Dev& d = s->d;
+  hipStream_t q = s->stream;
+  le_status st = hip_check(launch_kick_drift(d, q));
+  if (st == LE_OK) st = hip_check(launch_control(d, q));
+  if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+  int64_t ns = 0;
+  for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
+    const bool last = (k == nsteps);
+    const bool sample = sample_every > 0 && (k % sample_every) == 0;
+    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, nullptr));
+    if (st == LE_OK && sample) {
+      double* slot = stress_ring + 6 * (ns % ring_cap);
+      ++ns;
+      st = hip_check(launch_stress_final(d, q, slot, false));
+    }
+    if (st == LE_OK && !last) {
+      st = hip_check(launch_control(d, q));
+      if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+    }
+  }
+  return st;
+}
+
+le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step) {
+  if (!s) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  le_status st = hip_check(launch_rebuild(s->d, s->stream, true));
+  if (st == LE_OK && (x || u)) st = hip_check(launch_state_out(s->d, s->stream, x, u, nullptr, nullptr));
+  if (st == LE_OK && f) {
+    // the total force lives with the velocities; reuse the state scatter on it
+    Dev tmp = s->d;
+    tmp.vel[0] = s->d.frc[0];
+    tmp.vel[1] = s->d.frc[1];
+    st = hip_check(launch_state_out(tmp, s->stream, nullptr, f, nullptr, nullptr));
+  }
+  if (st == LE_OK) st = read_status(s);
+  if (st == LE_OK && step) {
+    if (hipMemcpy(step, &s->d.ctrl->step, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+      st = LE_E_HIP;
+  }
+  return st;
+}
+
+le_status le_sync(le_sim* s) {
+  if (!s) return LE_E_ARG;
+  return read_status(s);
+}
+
+le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors) {
+  if (!s) return LE_E_ARG;
+  le_status st = read_status(s);
+  Ctrl c;
+  if (hipMemcpy(&c, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return LE_E_HIP;
+  if (rebuilds) *rebuilds = c.n_rebuilds;
+  if (max_neighbors) *max_neighbors = c.max_nb;
+  return st;
+}
+
+le_status le_destroy(le_sim* s) {
+  if (!s) return LE_E_ARG;
+  delete s;
+  return LE_OK;
+}
+
+const char* le_strerror(le_status st) {
+  switch (st) {
+    case LE_OK: return "ok";
+    case LE_E_ARG: return "invalid argument";
+    case LE_E_GEOMETRY: return "box too small for the cutoff (need >= 3 cells of size >= rc+skin per axis)";
+    case LE_E_WORKSPACE: return "workspace smaller than le_workspace_bytes()";
+    case LE_E_BOND: return "FENE bond stretched to r >= R0";
+    case LE_E_NONFINITE: return "non-finite position or velocity";
+    case LE_E_CAPACITY: return "neighbour list over capacity (raise max_neighbors)";
+    case LE_E_HIP: return "HIP runtime error";
+    case LE_E_STATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+le_status le_offsets(double shear_rate, double Lx, double Ly, double dt, int64_t step0, int64_t count,
+                     double* out, void* hip_stream) {
+  if (!out || count < 0 || !(Lx > 0.0)) return LE_E_ARG;
+  return hip_check(launch_offsets(shear_rate, Lx, Ly, dt, step0, count, out, (hipStream_t)hip_stream));
+}
+
+le_status le_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                    void* hip_stream) {
+  if (!ctr || !key || !out || count < 0) return LE_E_ARG;
+  return hip_check(launch_philox(ctr, key, out, count, (hipStream_t)hip_stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// le_internal.h -- device-side layout shared by the host runtime and the
+// kernels of the Lees-Edwards library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "le.h"
+
+namespace le {
+
+constexpr int kBlock = 256;        // threads per block of the per-particle kernels
+constexpr int kScanChunk = 2048;   // cells per block of the cell-count scan
+constexpr int kStressComps = 12;   // 6 kinetic + 6 virial partial sums per block
+
+// Mutable per-simulation scalars that live on the device so that a step
+// never needs the host: step counter, offset, rebuild bookkeeping, status.
+struct alignas(64) Ctrl {
+  int64_t step;          // index n of the current state
+  int64_t rebuild_step;  // step of the last neighbour-list build (m)
+  int64_t n_rebuilds;
+  double Delta;          // offset of step n, in [0, L_x)
+  double Delta_ref;      // offset at the last build
+  double drift;          // sum over steps since the build of dt * max |peculiar velocity|
+  unsigned long long vmax_bits;  // running max of |c| in the current step (bits of a double >= 0)
+  int32_t pos_cur;       // which position buffer holds the current positions
+  int32_t aux_cur;       // which velocity/force/tag buffer is current
+  int32_t rebuild;       // 1: rebuild before the next force evaluation
+  int32_t status;        // sticky device status (LE_OK or an LE_E_* code)
+  int32_t wraps;         // whole L_x folds of the offset since the build
+  int32_t max_nb;        // largest neighbour count of the last build
+  int32_t pad[2];
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  // geometry and physics
+  double Lx, Ly, Lz;
+  double inv_lx, inv_ly, inv_lz;   // cells per unit length (n_a / L_a)
+  double lx;                       // cell length along x
+  double shear_rate, sv;           // gamma_dot and gamma_dot * L_y
+  double dt, h;                    // time step and dt / (2 m)
+  double gamma_m;                  // gamma * m
+  double pref;                     // sqrt(24 gamma m kT / dt)
+  double mass;
+  double eps24, sig2;              // 24 eps, sigma^2
+  double rc2, rlist, rlist2;       // cutoff^2, list radius, list radius^2
+  double fene_k, fene_r02;
+  double inv_vol;
+  int32_t nx, ny, nz, ncell;
+  int32_t n, np;                   // particles, padded stride
+  int32_t K;                       // neighbour capacity per particle
+  int32_t chain_len;
+  int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
+  int32_t precision;
+  uint32_t seed_lo, seed_hi;
+  int32_t nblocks;                 // blocks of the per-particle kernels
+  // buffers (device)
+  double* pos[2];                  // [3][np] each
+  double* vel[2];                  // [3][np]
+  double* frc[2];                  // [3][np] total force of the current step
+  int32_t* tag[2];                 // slot -> tag
+  int32_t* slot_of_tag;            // tag -> slot
+  int32_t* cell_of;                // cell of each slot (binning pass)
+  int32_t* rank;                   // arrival rank inside the cell (binning pass)
+  int32_t* src;                    // scatter target -> source slot
+  int32_t* cell_count;             // [ncell]
+  int32_t* cell_start;             // [ncell + 1]
+  int32_t* block_sums;             // [ceil(ncell / kScanChunk)]
+  int32_t* nl;                     // [K][np] neighbour slots; plain from row 0, imaged from row K-1 down
+  uint8_t* nlc;                    // [K][np] image code of imaged entries
+  int32_t* n_plain;                // [np]
+  int32_t* n_img;                  // [np]
+  int32_t* bond;                   // [2][np] slot of the chain neighbour below/above, -1 if none
+  double* partials;                // [nblocks][kStressComps]
+  Ctrl* ctrl;
+};
+
+// Image code of an imaged neighbour: sx in [-3, 3], sy and sz in [-1, 1].
+__host__ __device__ inline uint8_t pack_img(int sx, int sy, int sz) {
+  return (uint8_t)((sx + 3) | ((sy + 1) << 3) | ((sz + 1) << 5));
+}
+__host__ __device__ inline void unpack_img(uint8_t c, int& sx, int& sy, int& sz) {
+  sx = (int)(c & 7) - 3;
+  sy = (int)((c >> 3) & 3) - 1;
+  sz = (int)((c >> 5) & 3) - 1;
+}
+
+// Launchers (le_kernels.hip).  Each enqueues on `stream` and returns the
+// hipError_t of the launch.
+enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 };
+
+hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force);
+hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
+hipError_t launch_control(const Dev& d, hipStream_t s);
+hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
+                        double* virial_out);
+hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
+hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,
+                            int32_t* order);
+hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t cap,
+                            unsigned long long* counter);
+hipError_t launch_load_state(const Dev& d, hipStream_t s, const double* x0, const double* u0,
+                             const double* f0, int64_t step0, double Delta0);
+hipError_t launch_offsets(double sr, double Lx, double Ly, double dt, int64_t step0, int64_t count,
+                          double* out, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                         hipStream_t s);
+
+// Offset of step n: fmod(gamma_dot L_y * (n dt), L_x) folded into [0, L_x).
+// fmod is exact, so host and device agree bit for bit.
+__host__ __device__ inline double le_offset(int64_t n, double dt, double sv, double Lx) {
+  double t = (double)n * dt;
+  double d = fmod(sv * t, Lx);
+  if (d < 0.0) d += Lx;
+  if (d >= Lx) d -= Lx;
+  return d;
+}
+
+}  // namespace le
