@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Throughput of the Lees-Edwards shear-flow MD step on one MI355X.
+
+Workload (default): LJ fluid, N = 256,000 particles on 256,000 of the sites
+of a 64^3 simple-cubic lattice (seeded choice, jitter U(-0.05, 0.05)), density 0.8442, cutoff 2.5, T = 1, Langevin
+gamma = 1 on the peculiar velocity, shear rate 0.1 (flow x, gradient y),
+dt = 0.005, skin 0.3, float64, shear stress sampled every 10 steps.  One
+"step" is a full pass of the hot path: offset, rebuild test (and rebuild when
+due: crossing/wrap, sort, Lees-Edwards stencil, neighbour lists), pair forces,
+Langevin force, velocity Verlet, stress sample.
+
+Prints ONE JSON line.  `value` is particle-steps/s with the state resident in
+HBM.  The roofline entry is for the dominant kernel (the fused force /
+thermostat / integrator kernel), timed with HIP events on the simulation's
+stream during the timed region.  The CPU baseline is the FP64 oracle
+(oracle/) on a bounded sample of the same workload, single thread.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s per GPU + p50/p99 sweep latency; mixed vs FP64 at viscosity tol"
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector (also the unpacked FP32 vector rate)
+PEAK_HBM_GBS = 8000.0
+PAIR_FLOPS = 26.0             # per in-cutoff pair, counted once per unordered pair
+STEP_FLOPS = 40.0             # thermostat + velocity Verlet per particle
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def lj_params(n, shear_rate, precision, seed=21, skin=0.3):
+    from paper_2109_11083_amd import inputs
+    from paper_2109_11083_amd.sim import Params
+    w = inputs.lj_workload(n=n, shear_rate=shear_rate, seed=seed)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, skin=skin,
+               precision=precision, rc=2.5, dt=0.005, kT=1.0, gamma=1.0)
+    return w, p
+
+
+def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True):
+    import torch
+    from paper_2109_11083_amd import binding as B
+    from paper_2109_11083_amd.sim import Sim
+    w, p = lj_params(n, shear_rate, precision)
+    sim = Sim(p, w.x, w.u, step0=0)
+    ring = torch.zeros((max(steps // sample_every, 1), 6), dtype=torch.float64, device="cuda")
+    if warmup > 0:
+        wring = torch.zeros((max(warmup // sample_every, 1), 6), dtype=torch.float64, device="cuda")
+        sim.step(warmup, sample_every=sample_every, ring=wring)
+    sim.sync()
+    st0 = sim.stats()
+    B.le_timing_enable(sim.handle, timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, sample_every=sample_every, ring=ring)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = B.le_timing_read(sim.handle)
+    st1 = sim.stats()
+    sig = ring.cpu().numpy()
+    tail = sig[int(0.8 * len(sig)):]
+    eta = float(tail[:, 3].mean() / shear_rate) if shear_rate != 0 else None
+    eta_se = None
+    if len(tail) >= 20:
+        blocks = tail[: len(tail) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / shear_rate
+        eta_se = float(blocks.std(ddof=1) / math.sqrt(10))
+    out = dict(n=p.n, seconds=t1 - t0, steps=steps, value=p.n * steps / (t1 - t0),
+               ms_per_step=1e3 * (t1 - t0) / steps, phases=phases,
+               rebuilds=st1["rebuilds"] - st0["rebuilds"], max_neighbors=st1["max_neighbors"],
+               eta=eta, eta_se=eta_se, box=p.box, rc=p.rc)
+    sim.close()
+    return out
+
+
+def cpu_baseline(n, shear_rate, nsteps):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    w, p = lj_params(n, shear_rate, "fp64")
+    op = O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma,
+                       rc=p.rc, seed=p.seed)
+    sim = O.Sim(w.x, w.u, op, step0=0, method=1)
+    t0 = time.perf_counter()
+    sim.run(nsteps)
+    t1 = time.perf_counter()
+    return dict(value=p.n * nsteps / (t1 - t0), unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{nsteps} steps of the same {p.n}-particle LJ system (FP64 cell-list oracle, "
+                       f"1 thread, {t1 - t0:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--shear-rate", type=float, default=0.1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--n", type=int, default=256000,
+                    help="particles: n sites of a ceil(n^(1/3))^3 lattice (256000 -> 64^3)")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="no HIP events in the timed region (then no per-kernel roofline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU decomposition is a design, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"bench: LJ n={args.n} shear_rate={args.shear_rate} {args.precision} "
+        f"steps={args.steps} warmup={args.warmup}")
+    r = run_gpu(args.n, args.shear_rate, args.precision, args.steps, args.warmup,
+                timing=not args.no_timing)
+    log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
+        f"rebuilds={r['rebuilds']}, phases={r['phases']}")
+
+    force_ms, force_n = r["phases"]["force"]
+    roofline = None
+    if force_n > 0:
+        avg_force_s = force_ms / 1e3 / force_n
+        rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
+        pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
+        flops_pp = PAIR_FLOPS * pairs_pp / 2.0 + STEP_FLOPS
+        achieved = r["n"] * flops_pp / avg_force_s / 1e12
+        roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS,
+                        unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=None,
+                        kernel="k_force (fused pair force + Langevin + velocity Verlet)",
+                        avg_kernel_us=round(avg_force_s * 1e6, 3),
+                        flops_per_particle=round(flops_pp, 1))
+
+    extra = {}
+    if not args.no_extra:
+        for sr in (0.01, 1.0):
+            e = run_gpu(args.n, sr, args.precision, 2000, 100)
+            extra[f"shear_rate_{sr}"] = dict(value=e["value"], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
+                                             eta=e["eta"])
+            log(f"bench: shear_rate={sr}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        m = run_gpu(args.n, args.shear_rate, other, 2000, 100)
+        extra[f"{other}_value"] = m["value"]
+        fm, fn = m["phases"]["force"]
+        extra[f"{other}_force_kernel_us"] = 1e3 * fm / max(fn, 1)
+        log(f"bench: {other}: {m['value']:.4e} p-steps/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.n, args.shear_rate, args.cpu_steps)
+        log(f"bench: cpu oracle {cpu['value']:.4e} particle-steps/s")
+
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
+                        f"T=1, Langevin gamma=1 on peculiar velocity, shear_rate={args.shear_rate}, "
+                        f"dt=0.005, skin 0.3, {args.precision}",
+            "n_particles": r["n"],
+            "shear_rate": args.shear_rate,
+            "precision": args.precision,
+            "stress_sample_every": 10,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rebuilds_per_1000_steps": round(1000.0 * r["rebuilds"] / args.steps, 2),
+        "phase_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()},
+        "viscosity": {"eta": r["eta"], "block_se": r["eta_se"], "window": "last 20% of the timed steps"},
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,20 @@ le_status le_sync(le_sim* s);
  * le_init and the largest neighbour count seen at the last rebuild. */
 le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors);
 
+/* Phase timing: while enabled, le_step records a pair of HIP events on the
+ * simulation's stream around each launch group and accumulates the elapsed
+ * device time per phase: 0 the force kernel (pair + bond forces, thermostat
+ * and integrator, fused), 1 the rebuild chain (crossing/wrap, sort, stencil,
+ * neighbour lists; empty launches on steps without a rebuild), 2 step
+ * bookkeeping (offset, rebuild decision, first half-kick), 3 the stress
+ * reduction.  le_timing_enable(s, 1) resets the totals; creating events is
+ * the only host-side resource it takes. */
+le_status le_timing_enable(le_sim* s, int32_t enabled);
+
+/* Totals since the last enable (waits for the stream): ms[4] elapsed device
+ * milliseconds and launches[4] launch-group counts per phase (host arrays). */
+le_status le_timing_read(le_sim* s, double* ms, int64_t* launches);
+
 /* Release the handle.  The workspace is the caller's and is not touched. */
 le_status le_destroy(le_sim* s);
 

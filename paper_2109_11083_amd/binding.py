@@ -30,6 +30,7 @@ LE_MIXED = 1
 EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
+    "le_timing_enable", "le_timing_read",
 ]
 
 
@@ -94,6 +95,8 @@ def lib() -> C.CDLL:
     L.le_strerror.restype = C.c_char_p
     L.le_offsets.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, i64, i64, vp, vp]
     L.le_philox.argtypes = [vp, vp, vp, i64, vp]
+    L.le_timing_enable.argtypes = [vp, i32]
+    L.le_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -176,3 +179,18 @@ def le_offsets(shear_rate: float, Lx: float, Ly: float, dt: float, step0: int, c
 
 def le_philox(ctr: int, key: int, out: int, count: int, stream: int | None) -> None:
     check(lib().le_philox(ctr, key, out, count, stream), "le_philox")
+
+
+def le_timing_enable(sim: int, enabled: bool) -> None:
+    check(lib().le_timing_enable(sim, 1 if enabled else 0), "le_timing_enable")
+
+
+PHASES = ("force", "rebuild", "bookkeeping", "stress")
+
+
+def le_timing_read(sim: int):
+    """Per-phase device milliseconds and launch-group counts since enabling."""
+    ms = (C.c_double * 4)()
+    n = (C.c_int64 * 4)()
+    check(lib().le_timing_read(sim, ms, n), "le_timing_read")
+    return {PHASES[k]: (ms[k], n[k]) for k in range(4)}

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "le_internal.h"
 
@@ -17,6 +18,13 @@ struct le_sim {
   int32_t host_status;                 // last status seen by a synchronising call
   unsigned long long* counter;         // device scratch counter (pairs_out)
   double* scratch6;                    // device 6 doubles
+  // phase timing (le_timing_enable)
+  bool timing;
+  std::vector<hipEvent_t> ev;          // pairs (start, stop)
+  std::vector<int> ev_phase;           // phase of each recorded pair
+  size_t ev_used;                      // pairs recorded and not yet folded
+  double phase_ms[4];
+  int64_t phase_n[4];
 };
 
 namespace {
@@ -70,8 +78,8 @@ le_status validate(const le_params* p, Geometry* g) {
     g->K = (int32_t)ceil(2.0 * mean) + 32;
   }
   if (g->K > 4096) g->K = 4096;
-  g->np = (p->n + kBlock - 1) / kBlock * kBlock;
-  g->nblocks = (int32_t)(g->np / kBlock);
+  g->np = (p->n + 1 + kBlock - 1) / kBlock * kBlock;  // +1: sentinel slot
+  g->nblocks = (int32_t)((p->n + kBlock - 1) / kBlock);
   return LE_OK;
 }
 
@@ -161,6 +169,45 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
 
 le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
 
+constexpr size_t kMaxEventPairs = 4096;
+
+// Fold recorded event pairs into the per-phase totals (waits for the stream).
+le_status fold_events(le_sim* s) {
+  if (s->ev_used == 0) return LE_OK;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return LE_E_HIP;
+  for (size_t k = 0; k < s->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]) != hipSuccess) return LE_E_HIP;
+    s->phase_ms[s->ev_phase[k]] += ms;
+    s->phase_n[s->ev_phase[k]] += 1;
+  }
+  s->ev_used = 0;
+  return LE_OK;
+}
+
+// Record the start of a timed launch group; returns the pair index or -1.
+long begin_phase(le_sim* s, int phase) {
+  if (!s->timing) return -1;
+  if (s->ev_used == kMaxEventPairs && fold_events(s) != LE_OK) return -1;
+  size_t k = s->ev_used;
+  if (s->ev.size() < 2 * (k + 1)) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return -1; }
+    s->ev.push_back(a);
+    s->ev.push_back(b);
+    s->ev_phase.push_back(0);
+  }
+  s->ev_phase[k] = phase;
+  if (hipEventRecord(s->ev[2 * k], s->stream) != hipSuccess) return -1;
+  return (long)k;
+}
+
+void end_phase(le_sim* s, long k) {
+  if (k < 0) return;
+  if (hipEventRecord(s->ev[2 * k + 1], s->stream) == hipSuccess) s->ev_used = (size_t)k + 1;
+}
+
 le_status read_status(le_sim* s) {
   int32_t st = 0;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LE_E_HIP;
@@ -192,9 +239,12 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   if (st != LE_OK) return st;
   size_t need = carve(p, g, nullptr, nullptr, nullptr);
   if (ws_bytes < need) return LE_E_WORKSPACE;
-  le_sim* s = new (std::nothrow) le_sim;
+  le_sim* s = new (std::nothrow) le_sim();
   if (!s) return LE_E_ARG;
-  memset(s, 0, sizeof(*s));
+  s->host_status = 0;
+  s->timing = false;
+  s->ev_used = 0;
+  for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
   s->p = *p;
   s->p.rc = g.rc;
   s->stream = (hipStream_t)hip_stream;
@@ -259,22 +309,29 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   if (nsteps == 0) return LE_OK;
   const Dev& d = s->d;
   hipStream_t q = s->stream;
+  long ev = begin_phase(s, 2);
   le_status st = hip_check(launch_kick_drift(d, q));
-  if (st == LE_OK) st = hip_check(launch_control(d, q));
+  end_phase(s, ev);
+  ev = begin_phase(s, 1);
   if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+  end_phase(s, ev);
   int64_t ns = 0;
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
     const bool last = (k == nsteps);
     const bool sample = sample_every > 0 && (k % sample_every) == 0;
-    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, nullptr));
-    if (st == LE_OK && sample) {
-      double* slot = stress_ring + 6 * (ns % ring_cap);
+    double* slot = nullptr;
+    if (sample) {
+      slot = stress_ring + 6 * (ns % ring_cap);
       ++ns;
-      st = hip_check(launch_stress_final(d, q, slot, false));
     }
+    // the force kernel also advances the step and reduces the stress sample
+    ev = begin_phase(s, 0);
+    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, slot));
+    end_phase(s, ev);
     if (st == LE_OK && !last) {
-      st = hip_check(launch_control(d, q));
-      if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+      ev = begin_phase(s, 1);
+      st = hip_check(launch_rebuild(d, q, false));
+      end_phase(s, ev);
     }
   }
   return st;
@@ -315,8 +372,28 @@ le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors) {
   return st;
 }
 
+le_status le_timing_enable(le_sim* s, int32_t enabled) {
+  if (!s) return LE_E_ARG;
+  le_status st = fold_events(s);
+  s->timing = enabled != 0;
+  for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
+  return st;
+}
+
+le_status le_timing_read(le_sim* s, double* ms, int64_t* launches) {
+  if (!s) return LE_E_ARG;
+  le_status st = fold_events(s);
+  for (int k = 0; k < 4; ++k) {
+    if (ms) ms[k] = s->phase_ms[k];
+    if (launches) launches[k] = s->phase_n[k];
+  }
+  return st;
+}
+
 le_status le_destroy(le_sim* s) {
   if (!s) return LE_E_ARG;
+  if (s->ev_used) (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   delete s;
   return LE_OK;
 }

@@ -29,7 +29,8 @@ struct alignas(64) Ctrl {
   int32_t status;        // sticky device status (LE_OK or an LE_E_* code)
   int32_t wraps;         // whole L_x folds of the offset since the build
   int32_t max_nb;        // largest neighbour count of the last build
-  int32_t pad[2];
+  uint32_t ticket;       // blocks finished in the current kernel (last-block pattern)
+  int32_t pad;
 };
 
 // Everything a kernel needs, passed by value.
@@ -48,7 +49,7 @@ struct Dev {
   double fene_k, fene_r02;
   double inv_vol;
   int32_t nx, ny, nz, ncell;
-  int32_t n, np;                   // particles, padded stride
+  int32_t n, np;                   // particles, padded stride (np > n: slot n is a far-away sentinel)
   int32_t K;                       // neighbour capacity per particle
   int32_t chain_len;
   int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
@@ -56,7 +57,7 @@ struct Dev {
   uint32_t seed_lo, seed_hi;
   int32_t nblocks;                 // blocks of the per-particle kernels
   // buffers (device)
-  double* pos[2];                  // [3][np] each
+  double* pos[2];                  // double4 [np] each (x, y, z, unused)
   double* vel[2];                  // [3][np]
   double* frc[2];                  // [3][np] total force of the current step
   int32_t* tag[2];                 // slot -> tag
@@ -92,9 +93,8 @@ enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 
 
 hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
-hipError_t launch_control(const Dev& d, hipStream_t s);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
-                        double* virial_out);
+                        double* sample_out);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,
                             int32_t* order);

@@ -96,6 +96,12 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     }
     d.tag[0][i] = i;
   }
+  if (i == 0) {
+    // far-away sentinel at slot n pads neighbour batches: r^2 ~ 1e200 never passes a cutoff
+    const double4 far = make_double4(1e100, 1e100, 1e100, 0.0);
+    reinterpret_cast<double4*>(d.pos[0])[n] = far;
+    reinterpret_cast<double4*>(d.pos[1])[n] = far;
+  }
   for (int c = i; c < d.ncell; c += gridDim.x * blockDim.x) d.cell_count[c] = 0;
   if (i == 0) {
     Ctrl* c = d.ctrl;
@@ -112,6 +118,7 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     c->status = 0;
     c->wraps = 0;
     c->max_nb = 0;
+    c->ticket = 0u;
   }
 }
 
@@ -261,12 +268,20 @@ __global__ void k_rank_permute(Dev d, int force) {
 // at most four cells for l >= r (five with the rounding margin).  Each
 // (cell, image) pair is visited once; with L > 2 r_list at most one image of
 // a particle can lie within r_list, so no pair is counted twice.
+//
+// Cells of one row that are adjacent in memory and share an image are
+// scanned as one contiguous slot range, four candidates per batch so that
+// several gathers are in flight.  Lists are padded with the sentinel slot n:
+// plain entries to a multiple of kPlainBatch, imaged ones to kImgBatch.
+constexpr int kPlainBatch = 8;
+constexpr int kImgBatch = 4;
+
 __global__ void __launch_bounds__(kBlock) k_neighbors(Dev d, int force) {
   if (rebuild_off(d, force)) return;
   Ctrl* c = d.ctrl;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const int np = d.np, K = d.K;
+  const int np = d.np, K = d.K, n = d.n;
   const int pn = 1 - c->pos_cur, an = 1 - c->aux_cur;
   const double4* P = reinterpret_cast<const double4*>(d.pos[pn]);
   const double Delta = c->Delta;
@@ -293,48 +308,73 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(Dev d, int force) {
         klo = (int)floor(((double)ix * d.lx - rmarg - sh) / d.lx);
         khi = (int)floor(((double)(ix + 1) * d.lx + rmarg - sh) / d.lx);
       }
-      for (int k = klo; k <= khi; ++k) {
+      const int rowbase = (jz * d.ny + jy) * d.nx;
+      const double shy = (double)sy * d.Ly;
+      const double shd = (double)sy * Delta;
+      const double shz = (double)sz * d.Lz;
+      int k = klo;
+      while (k <= khi) {
+        // one segment: cells k .. kend with the same x image
         int sx = floor_div(k, d.nx);
-        int jx = k - sx * d.nx;
-        int cell = (jz * d.ny + jy) * d.nx + jx;
-        int q0 = d.cell_start[cell], q1 = d.cell_start[cell + 1];
+        int kend = (sx + 1) * d.nx - 1;
+        if (kend > khi) kend = khi;
+        const int c0 = rowbase + (k - sx * d.nx);
+        const int c1 = rowbase + (kend - sx * d.nx);
+        const int q0 = d.cell_start[c0], q1 = d.cell_start[c1 + 1];
         const bool plain = (sx == 0 && sy == 0 && sz == 0);
-        const double shy = (double)sy * d.Ly;
-        const double shd = (double)sy * Delta;
         const double shx = (double)sx * d.Lx;
-        const double shz = (double)sz * d.Lz;
-        for (int q = q0; q < q1; ++q) {
-          if (plain && q == i) continue;
-          double4 pj = P[q];
-          double dy = (pi.y - pj.y) - shy;
-          double dx = ((pi.x - pj.x) - shd) - shx;
-          double dz = (pi.z - pj.z) - shz;
-          double r2 = dx * dx + dy * dy;
-          r2 = r2 + dz * dz;
-          if (r2 < rl2) {
-            if (npl + nim < K) {
-              if (plain) {
-                d.nl[npl * np + i] = q;
-              } else {
-                int row = K - 1 - nim;
-                d.nl[row * np + i] = q;
-                d.nlc[row * np + i] = pack_img(sx, sy, sz);
+        const uint8_t code = pack_img(sx, sy, sz);
+        for (int q = q0; q < q1; q += 4) {
+          int qq[4];
+          double4 pj[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            qq[u] = (q + u < q1) ? q + u : n;
+            pj[u] = P[qq[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            double dy = (pi.y - pj[u].y) - shy;
+            double dx = ((pi.x - pj[u].x) - shd) - shx;
+            double dz = (pi.z - pj[u].z) - shz;
+            double r2 = dx * dx + dy * dy;
+            r2 = r2 + dz * dz;
+            if (r2 < rl2 && !(plain && qq[u] == i)) {
+              if (npl + nim < K) {
+                if (plain) {
+                  d.nl[npl * np + i] = qq[u];
+                } else {
+                  int row = K - 1 - nim;
+                  d.nl[row * np + i] = qq[u];
+                  d.nlc[row * np + i] = code;
+                }
               }
+              if (plain) ++npl; else ++nim;
             }
-            if (plain) ++npl; else ++nim;
           }
         }
+        k = kend + 1;
       }
     }
   }
-  if (npl + nim > K) {
+  atomicMax(&c->max_nb, npl + nim);
+  // pad both parts to whole batches with the sentinel
+  int npl_p = (npl + kPlainBatch - 1) / kPlainBatch * kPlainBatch;
+  int nim_p = (nim + kImgBatch - 1) / kImgBatch * kImgBatch;
+  if (npl_p + nim_p > K) {
     latch(c, LE_E_CAPACITY);
-    npl = npl < K ? npl : K;
-    nim = 0;
+    npl_p = 0;
+    nim_p = 0;
+  } else {
+    for (int r = npl; r < npl_p; ++r) d.nl[r * np + i] = n;
+    const uint8_t zero = pack_img(0, 0, 0);
+    for (int r = nim; r < nim_p; ++r) {
+      d.nl[(K - 1 - r) * np + i] = n;
+      d.nlc[(K - 1 - r) * np + i] = zero;
+    }
   }
-  d.n_plain[i] = npl;
-  d.n_img[i] = nim;
-  atomicMax(&c->max_nb, npl + nim);  // (clipped on overflow; the status already says so)
+  d.n_plain[i] = npl_p;
+  d.n_img[i] = nim_p;
   if (d.chain_len > 0) {
     int t = d.tag[an][i];
     int lo = -1, hi = -1;
@@ -367,8 +407,80 @@ __device__ __forceinline__ void vmax_commit(Ctrl* c, double v2) {
   if ((threadIdx.x & 63) == 0) atomicMax(&c->vmax_bits, (unsigned long long)__double_as_longlong(m));
 }
 
+// Advance the step counter and the offset, adopt the new positions, and
+// decide whether the neighbour lists must be rebuilt before the next force
+// evaluation.  Pair displacements evolve as d' = d + dt (c_i - c_j) +
+// gamma_dot dt d_y e_x, so after a strain s = |gamma_dot| (t - t_build) and a
+// peculiar path bound D = sum dt max|c|, a pair within rc now was within
+// g (rc + 2 g D) at the build, g = s/2 + sqrt(1 + s^2/4) the norm of the
+// inverse shear.  The lists (radius rc + skin) stay complete while that bound
+// is below rc + skin.  Runs on one thread after every block of the drift
+// kernel has finished.
+__device__ void control_update(const Dev& d, Ctrl* c) {
+  double vmax = sqrt(__longlong_as_double((long long)c->vmax_bits));
+  c->vmax_bits = 0ull;
+  c->drift += d.dt * vmax;
+  c->step += 1;
+  c->Delta = le_offset(c->step, d.dt, d.sv, d.Lx);
+  c->pos_cur ^= 1;
+  double T = (double)(c->step - c->rebuild_step) * d.dt;
+  c->wraps = (int)rint((c->Delta_ref + d.sv * T - c->Delta) / d.Lx);
+  double s = fabs(d.shear_rate) * T;
+  double g = 0.5 * s + sqrt(1.0 + 0.25 * s * s);
+  double rc = sqrt(d.rc2);
+  double need = g * (rc + 2.0 * g * c->drift);
+  if (d.rlist <= rc || need >= d.rlist * (1.0 - 1e-9)) c->rebuild = 1;
+}
+
+// Last-block pattern: every block publishes its writes and takes a ticket;
+// the block that takes the final ticket sees all of them.  Returns true in
+// every thread of that block.
+__device__ __forceinline__ bool last_block(Ctrl* c) {
+  __shared__ int is_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = atomicAdd(&c->ticket, 1u);
+    is_last = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+// Sum the per-block stress partials (fixed order) and write the stress
+// -(K + W)/V, or with virial_only the pair virial W, into out6.  Called by one
+// whole block.
+__device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
+  __shared__ double red[kBlock / 64][kStressComps];
+  double acc[kStressComps];
+#pragma unroll
+  for (int k = 0; k < kStressComps; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < d.nblocks; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kStressComps; ++k) acc[k] += d.partials[b * kStressComps + k];
+  }
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kStressComps; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[wid][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double kin = 0.0, vir = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      kin += red[w][threadIdx.x];
+      vir += red[w][6 + threadIdx.x];
+    }
+    out6[threadIdx.x] = virial_only ? vir : -(kin + vir) * d.inv_vol;
+  }
+}
+
 // First half-kick and drift from a state with full-step velocities:
-// u += dt/(2m) F ; x_new = x + dt u (into the other position buffer).
+// u += dt/(2m) F ; x_new = x + dt u (into the other position buffer); the
+// last block then advances the step (control_update).
 __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
   __shared__ int skip;
   Ctrl* c = d.ctrl;
@@ -398,31 +510,10 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(c, LE_E_NONFINITE);
   }
   vmax_commit(c, v2);
-}
-
-// Advance the step counter and the offset, adopt the new positions, and
-// decide whether the neighbour lists must be rebuilt before the next force
-// evaluation.  Pair displacements evolve as d' = d + dt (c_i - c_j) +
-// gamma_dot dt d_y e_x, so after a strain s = |gamma_dot| (t - t_build) and a
-// peculiar path bound D = sum dt max|c|, a pair within rc now was within
-// g (rc + 2 g D) at the build, g = s/2 + sqrt(1 + s^2/4) the norm of the
-// inverse shear.  The lists (radius rc + skin) stay complete while that bound
-// is below rc + skin.
-__global__ void k_control(Dev d, double rc, double skin) {
-  Ctrl* c = d.ctrl;
-  if (c->status) return;
-  double vmax = sqrt(__longlong_as_double((long long)c->vmax_bits));
-  c->vmax_bits = 0ull;
-  c->drift += d.dt * vmax;
-  c->step += 1;
-  c->Delta = le_offset(c->step, d.dt, d.sv, d.Lx);
-  c->pos_cur ^= 1;
-  double T = (double)(c->step - c->rebuild_step) * d.dt;
-  c->wraps = (int)rint((c->Delta_ref + d.sv * T - c->Delta) / d.Lx);
-  double s = fabs(d.shear_rate) * T;
-  double g = 0.5 * s + sqrt(1.0 + 0.25 * s * s);
-  double need = g * (rc + 2.0 * g * c->drift);
-  if (skin <= 0.0 || need >= d.rlist * (1.0 - 1e-9)) c->rebuild = 1;
+  if (last_block(c) && threadIdx.x == 0) {
+    control_update(d, c);
+    c->ticket = 0u;
+  }
 }
 
 // ---------------------------------------------------------- force kernel
@@ -482,7 +573,8 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE>
-__global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_out) {
+__global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_out,
+                                                  double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
   __shared__ int skip;
   Ctrl* c = d.ctrl;
@@ -503,30 +595,54 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_
   if (valid) {
     pi = P[i];
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
-    const int npl = d.n_plain[i];
+    const int npl = d.n_plain[i];  // a multiple of kPlainBatch (sentinel-padded)
     const int* __restrict__ nl = d.nl + i;
-    for (int k = 0; k < npl; ++k) {
-      int j = nl[k * np];
-      double4 pj = P[j];
-      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-      double r2 = dx * dx + dy * dy;
-      r2 = r2 + dz * dz;
-      if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+    int jn[kPlainBatch];
+    if (npl > 0) {
+#pragma unroll
+      for (int u = 0; u < kPlainBatch; ++u) jn[u] = nl[u * np];
     }
-    const int nim = d.n_img[i];
-    for (int k = 0; k < nim; ++k) {
-      int row = K - 1 - k;
-      int j = nl[row * np];
-      int sx, sy, sz;
-      unpack_img(d.nlc[row * np + i], sx, sy, sz);
-      sx += sy * W;
-      double4 pj = P[j];
-      double dy = (pi.y - pj.y) - (double)sy * d.Ly;
-      double dx = ((pi.x - pj.x) - (double)sy * Delta) - (double)sx * d.Lx;
-      double dz = (pi.z - pj.z) - (double)sz * d.Lz;
-      double r2 = dx * dx + dy * dy;
-      r2 = r2 + dz * dz;
-      if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+    for (int k = 0; k < npl; k += kPlainBatch) {
+      double4 pj[kPlainBatch];
+#pragma unroll
+      for (int u = 0; u < kPlainBatch; ++u) pj[u] = P[jn[u]];
+      if (k + kPlainBatch < npl) {
+#pragma unroll
+        for (int u = 0; u < kPlainBatch; ++u) jn[u] = nl[(k + kPlainBatch + u) * np];
+      }
+#pragma unroll
+      for (int u = 0; u < kPlainBatch; ++u) {
+        double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
+        double r2 = dx * dx + dy * dy;
+        r2 = r2 + dz * dz;
+        if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+      }
+    }
+    const int nim = d.n_img[i];  // a multiple of kImgBatch
+    for (int k = 0; k < nim; k += kImgBatch) {
+      int jj[kImgBatch];
+      uint8_t cc[kImgBatch];
+      double4 pj[kImgBatch];
+#pragma unroll
+      for (int u = 0; u < kImgBatch; ++u) {
+        int row = K - 1 - (k + u);
+        jj[u] = nl[row * np];
+        cc[u] = d.nlc[row * np + i];
+      }
+#pragma unroll
+      for (int u = 0; u < kImgBatch; ++u) pj[u] = P[jj[u]];
+#pragma unroll
+      for (int u = 0; u < kImgBatch; ++u) {
+        int sx, sy, sz;
+        unpack_img(cc[u], sx, sy, sz);
+        sx += sy * W;
+        double dy = (pi.y - pj[u].y) - (double)sy * d.Ly;
+        double dx = ((pi.x - pj[u].x) - (double)sy * Delta) - (double)sx * d.Lx;
+        double dz = (pi.z - pj[u].z) - (double)sz * d.Lz;
+        double r2 = dx * dx + dy * dy;
+        r2 = r2 + dz * dz;
+        if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+      }
     }
     if (BONDS) {
       // FENE (Eq. fene), always float64; displacement by the nearest image
@@ -615,36 +731,24 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.5 * w[k]; }
     block_partials(vals, d.partials, lb);
   }
+  if (MODE == kStepFused || (MODE == kStepLast && SAMPLE)) {
+    if (last_block(c)) {
+      if (SAMPLE) reduce_partials(d, sample_out, false);
+      if (threadIdx.x == 0) {
+        if (MODE == kStepFused) control_update(d, c);
+        c->ticket = 0u;
+      }
+    }
+  }
 }
 
-// Sum the block partials in a fixed order.  out6 receives either the stress
-// -(K + W)/V (Eq. tensor) or, with virial_only, the pair virial W.
+// Stand-alone reduction of the block partials (le_forces, le_stress).
 __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
-  __shared__ double red[kBlock];
   __shared__ int skip;
   if (threadIdx.x == 0) skip = d.ctrl->status;
   __syncthreads();
   if (skip) return;
-  for (int comp = 0; comp < kStressComps; ++comp) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < d.nblocks; b += kBlock) s += d.partials[b * kStressComps + comp];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (virial_only) {
-        if (comp >= 6) out6[comp - 6] = red[0];
-      } else {
-        // kinetic first (comp < 6): stash, add the virial when it arrives
-        if (comp < 6) out6[comp] = red[0];
-        else out6[comp - 6] = -(out6[comp - 6] + red[0]) * d.inv_vol;
-      }
-    }
-    __syncthreads();
-  }
+  reduce_partials(d, out6, virial_only != 0);
 }
 
 // ----------------------------------------------------------- state out
@@ -729,38 +833,32 @@ hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_control(const Dev& d, hipStream_t s) {
-  double rc = sqrt(d.rc2);
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, d, rc, d.rlist - rc);
-  return hipGetLastError();
-}
-
 template <int MODE, bool SAMPLE>
-static void launch_force_t(const Dev& d, hipStream_t s, double* f_out) {
+static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so) {
   dim3 g(d.nblocks), b(kBlock);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, true, true, SAMPLE>), g, b, 0, s, d, f_out);
-    else hipLaunchKernelGGL((k_force<MODE, true, false, SAMPLE>), g, b, 0, s, d, f_out);
+    if (bonds) hipLaunchKernelGGL((k_force<MODE, true, true, SAMPLE>), g, b, 0, s, d, f_out, so);
+    else hipLaunchKernelGGL((k_force<MODE, true, false, SAMPLE>), g, b, 0, s, d, f_out, so);
   } else {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, false, true, SAMPLE>), g, b, 0, s, d, f_out);
-    else hipLaunchKernelGGL((k_force<MODE, false, false, SAMPLE>), g, b, 0, s, d, f_out);
+    if (bonds) hipLaunchKernelGGL((k_force<MODE, false, true, SAMPLE>), g, b, 0, s, d, f_out, so);
+    else hipLaunchKernelGGL((k_force<MODE, false, false, SAMPLE>), g, b, 0, s, d, f_out, so);
   }
 }
 
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
-                        double* /*virial_out*/) {
+                        double* sample_out) {
   switch (mode) {
-    case kForcesOnly: launch_force_t<kForcesOnly, false>(d, s, f_out); break;
-    case kInitForce: launch_force_t<kInitForce, false>(d, s, f_out); break;
+    case kForcesOnly: launch_force_t<kForcesOnly, false>(d, s, f_out, nullptr); break;
+    case kInitForce: launch_force_t<kInitForce, false>(d, s, f_out, nullptr); break;
     case kStepLast:
-      if (sample) launch_force_t<kStepLast, true>(d, s, f_out);
-      else launch_force_t<kStepLast, false>(d, s, f_out);
+      if (sample) launch_force_t<kStepLast, true>(d, s, f_out, sample_out);
+      else launch_force_t<kStepLast, false>(d, s, f_out, nullptr);
       break;
     case kStepFused:
-      if (sample) launch_force_t<kStepFused, true>(d, s, f_out);
-      else launch_force_t<kStepFused, false>(d, s, f_out);
+      if (sample) launch_force_t<kStepFused, true>(d, s, f_out, sample_out);
+      else launch_force_t<kStepFused, false>(d, s, f_out, nullptr);
       break;
   }
   return hipGetLastError();
