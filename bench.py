@@ -47,11 +47,11 @@ def lj_params(n, shear_rate, precision, seed=21, skin=0.3):
     return w, p
 
 
-def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True):
+def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True, skin=0.3):
     import torch
     from paper_2109_11083_amd import binding as B
     from paper_2109_11083_amd.sim import Sim
-    w, p = lj_params(n, shear_rate, precision)
+    w, p = lj_params(n, shear_rate, precision, skin=skin)
     sim = Sim(p, w.x, w.u, step0=0)
     ring = torch.zeros((max(steps // sample_every, 1), 6), dtype=torch.float64, device="cuda")
     if warmup > 0:

@@ -78,8 +78,9 @@ le_status validate(const le_params* p, Geometry* g) {
     g->K = (int32_t)ceil(2.0 * mean) + 32;
   }
   if (g->K > 4096) g->K = 4096;
+  g->K = (g->K + 7) / 8 * 8;  // lists are stored in blocks of 8 (plain) and 4 (other) entries
   g->np = (p->n + 1 + kBlock - 1) / kBlock * kBlock;  // +1: sentinel slot
-  g->nblocks = (int32_t)((p->n + kBlock - 1) / kBlock);
+  g->nblocks = (int32_t)((p->n + kTile - 1) / kTile);
   return LE_OK;
 }
 
@@ -110,10 +111,14 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
   t.block_sums = (int32_t*)take(nchunks * sizeof(int32_t));
-  t.nl = (int32_t*)take((size_t)g.K * np * sizeof(int32_t));
+  t.nl16 = (uint16_t*)take((size_t)g.K * np * sizeof(uint16_t));
+  t.nlo = (uint32_t*)take((size_t)g.K * np * sizeof(uint32_t));
   t.nlc = (uint8_t*)take((size_t)g.K * np);
   t.n_plain = (int32_t*)take(np * sizeof(int32_t));
-  t.n_img = (int32_t*)take(np * sizeof(int32_t));
+  t.n_og = (int32_t*)take(np * sizeof(int32_t));
+  t.halo_slot = (int32_t*)take((size_t)g.nblocks * kHalo * sizeof(int32_t));
+  t.halo_code = (uint8_t*)take((size_t)g.nblocks * kHalo);
+  t.tile_nstage = (int32_t*)take((size_t)g.nblocks * sizeof(int32_t));
   t.bond = (p->chain_len > 0) ? (int32_t*)take(2 * np * sizeof(int32_t)) : nullptr;
   t.partials = (double*)take((size_t)g.nblocks * kStressComps * sizeof(double));
   unsigned long long* counter = (unsigned long long*)take(sizeof(unsigned long long));
@@ -126,7 +131,10 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     }
     d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->src = t.src;
     d->cell_count = t.cell_count; d->cell_start = t.cell_start; d->block_sums = t.block_sums;
-    d->nl = t.nl; d->nlc = t.nlc; d->n_plain = t.n_plain; d->n_img = t.n_img; d->bond = t.bond;
+    d->nl16 = t.nl16; d->nlo = t.nlo; d->nlc = t.nlc;
+    d->n_plain = t.n_plain; d->n_og = t.n_og;
+    d->halo_slot = t.halo_slot; d->halo_code = t.halo_code; d->tile_nstage = t.tile_nstage;
+    d->bond = t.bond;
     d->partials = t.partials;
   }
   if (s) { s->counter = counter; s->scratch6 = scratch6; }
@@ -153,6 +161,24 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->rc2 = g.rc * g.rc;
   d->rlist = g.rlist;
   d->rlist2 = g.rlist * g.rlist;
+  {
+    // Bound on |r2_f32 - r2_f64| for a pair near the list radius.  Staged
+    // coordinates are relative to a tile particle and image-shifted, so each
+    // lies within 4 L_max + r_list of zero; rounding each to float moves it by
+    // at most 2^-24 of that, a displacement component by delta = twice that,
+    // r2 by 2 sqrt(3) (r_list + delta) delta + 3 delta^2, and the three float
+    // operations forming r2 add 3 ulps of r_list^2.  Doubled for safety.
+    const double lmax = fmax(p->box[0], fmax(p->box[1], p->box[2]));
+    const double u = ldexp(1.0, -24);
+    const double delta = 2.0 * u * (4.0 * lmax + g.rlist);
+    const double rl2 = g.rlist * g.rlist;
+    const double margin = 2.0 * (2.0 * sqrt(3.0) * (g.rlist + delta) * delta + 3.0 * delta * delta +
+                                 4.0 * u * rl2 * 1.01) + 1e-12 * rl2;
+    d->nb_lo = nextafterf((float)(rl2 - margin), 0.0f);
+    d->nb_hi = nextafterf((float)(rl2 + margin), INFINITY);
+    if ((double)d->nb_lo + margin > rl2) d->nb_lo = nextafterf(d->nb_lo, 0.0f);
+    if ((double)d->nb_hi - margin < rl2) d->nb_hi = nextafterf(d->nb_hi, INFINITY);
+  }
   d->fene_k = p->fene_k;
   d->fene_r02 = p->fene_r0 * p->fene_r0;
   d->inv_vol = 1.0 / (p->box[0] * p->box[1] * p->box[2]);
@@ -165,6 +191,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->seed_lo = (uint32_t)p->seed;
   d->seed_hi = (uint32_t)(p->seed >> 32);
   d->nblocks = g.nblocks;
+  d->ntiles = g.nblocks;
 }
 
 le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
@@ -311,6 +338,7 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   hipStream_t q = s->stream;
   long ev = begin_phase(s, 2);
   le_status st = hip_check(launch_kick_drift(d, q));
+  if (st == LE_OK) st = hip_check(launch_control(d, q));
   end_phase(s, ev);
   ev = begin_phase(s, 1);
   if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
@@ -319,18 +347,22 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
     const bool last = (k == nsteps);
     const bool sample = sample_every > 0 && (k % sample_every) == 0;
-    double* slot = nullptr;
-    if (sample) {
-      slot = stress_ring + 6 * (ns % ring_cap);
-      ++ns;
-    }
-    // the force kernel also advances the step and reduces the stress sample
     ev = begin_phase(s, 0);
-    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, slot));
+    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, nullptr));
     end_phase(s, ev);
+    if (st == LE_OK && sample) {
+      double* slot = stress_ring + 6 * (ns % ring_cap);
+      ++ns;
+      ev = begin_phase(s, 3);
+      st = hip_check(launch_stress_final(d, q, slot, false));
+      end_phase(s, ev);
+    }
     if (st == LE_OK && !last) {
+      ev = begin_phase(s, 2);
+      st = hip_check(launch_control(d, q));
+      end_phase(s, ev);
       ev = begin_phase(s, 1);
-      st = hip_check(launch_rebuild(d, q, false));
+      if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
       end_phase(s, ev);
     }
   }

@@ -9,7 +9,13 @@
 
 namespace le {
 
-constexpr int kBlock = 256;        // threads per block of the per-particle kernels
+constexpr int kBlock = 256;        // threads per block of the streaming per-particle kernels
+constexpr int kTile = 128;         // particles (= threads) per tile of the pair kernels
+constexpr int kHalo = 2048;        // positions a tile stages in LDS (slot kHalo: far sentinel)
+constexpr int kMaxRows = 3;        // cell rows a tile may span and still be staged
+constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile
+constexpr int kPlainBatch = 8;     // padding of the plain list (LDS gathers in flight)
+constexpr int kOtherBatch = 4;     // padding of the imaged / global lists
 constexpr int kScanChunk = 2048;   // cells per block of the cell-count scan
 constexpr int kStressComps = 12;   // 6 kinetic + 6 virial partial sums per block
 
@@ -29,7 +35,7 @@ struct alignas(64) Ctrl {
   int32_t status;        // sticky device status (LE_OK or an LE_E_* code)
   int32_t wraps;         // whole L_x folds of the offset since the build
   int32_t max_nb;        // largest neighbour count of the last build
-  uint32_t ticket;       // blocks finished in the current kernel (last-block pattern)
+  uint32_t spare;
   int32_t pad;
 };
 
@@ -54,8 +60,12 @@ struct Dev {
   int32_t chain_len;
   int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
   int32_t precision;
+  // FP32 pre-test of the list build: r2 (float, tile-relative coordinates)
+  // below nb_lo is certainly inside r_list^2, at or above nb_hi certainly
+  // outside; in between the plain FP64 displacement decides.
+  float nb_lo, nb_hi;
   uint32_t seed_lo, seed_hi;
-  int32_t nblocks;                 // blocks of the per-particle kernels
+  int32_t nblocks;                 // blocks of the pair kernels (= ntiles)
   // buffers (device)
   double* pos[2];                  // double4 [np] each (x, y, z, unused)
   double* vel[2];                  // [3][np]
@@ -68,12 +78,25 @@ struct Dev {
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
   int32_t* block_sums;             // [ceil(ncell / kScanChunk)]
-  int32_t* nl;                     // [K][np] neighbour slots; plain from row 0, imaged from row K-1 down
-  uint8_t* nlc;                    // [K][np] image code of imaged entries
-  int32_t* n_plain;                // [np]
-  int32_t* n_img;                  // [np]
+  // Neighbour lists.  Entry k of particle i lives in a block of consecutive
+  // entries of that particle: blocks of 8 (one 16-byte load) for nl16, of 4
+  // for nlo/nlc; block b of particles i, i+1, ... is contiguous.
+  //   nl16  partners staged in the tile's LDS halo (any image): LDS index,
+  //         element k at ((k/8)*np + i)*8 + k%8
+  //   nlo   partners not staged: slot in global memory, element k at
+  //         ((k/4)*np + i)*4 + k%4
+  //   nlc   image code of each nlo entry, same layout (bytes)
+  uint16_t* nl16;
+  uint32_t* nlo;
+  uint8_t* nlc;
+  int32_t* n_plain;                // [np] staged entries, multiple of kPlainBatch
+  int32_t* n_og;                   // [np] global entries, multiple of kOtherBatch
+  int32_t* halo_slot;              // [ntiles][kHalo] slot staged at each LDS position
+  uint8_t* halo_code;              // [ntiles][kHalo] image code of each staged position
+  int32_t* tile_nstage;            // [ntiles] staged positions per tile
+  int32_t ntiles;
   int32_t* bond;                   // [2][np] slot of the chain neighbour below/above, -1 if none
-  double* partials;                // [nblocks][kStressComps]
+  double* partials;                // [nblocks][kStressComps] (nblocks = ntiles)
   Ctrl* ctrl;
 };
 
@@ -93,6 +116,7 @@ enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 
 
 hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
+hipError_t launch_control(const Dev& d, hipStream_t s);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
                         double* sample_out);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);

@@ -118,7 +118,7 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     c->status = 0;
     c->wraps = 0;
     c->max_nb = 0;
-    c->ticket = 0u;
+    c->spare = 0u;
   }
 }
 
@@ -269,119 +269,391 @@ __global__ void k_rank_permute(Dev d, int force) {
 // (cell, image) pair is visited once; with L > 2 r_list at most one image of
 // a particle can lie within r_list, so no pair is counted twice.
 //
-// Cells of one row that are adjacent in memory and share an image are
-// scanned as one contiguous slot range, four candidates per batch so that
-// several gathers are in flight.  Lists are padded with the sentinel slot n:
-// plain entries to a multiple of kPlainBatch, imaged ones to kImgBatch.
-constexpr int kPlainBatch = 8;
-constexpr int kImgBatch = 4;
+// Tiles.  The particles of one tile (kTile consecutive cell-sorted slots)
+// span a few cell rows.  For every covered row r, offset (dy, dz) and x-image
+// sx, the cells the tile's stencils can reach in the neighbouring row form a
+// contiguous slot range (a "piece").  The pieces are staged into LDS in a
+// fixed order while they fit (kHalo positions); halo_slot records the slot
+// at every LDS position so that the force kernel can restage the same halo
+// each step.  Pairs whose partner is staged store its LDS index (16 bits
+// without image, 32 bits + code with one); pairs into unstaged pieces store
+// the partner's slot.  Lists are padded with sentinels (LDS index kHalo,
+// slot n) to whole batches.
 
-__global__ void __launch_bounds__(kBlock) k_neighbors(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
+struct TileGeom {
+  int row_first, nrows, staged_ok;
+  int c_first, c_last;
+};
+
+// Element k of particle i in the blocked list layouts (see Dev).
+__device__ __forceinline__ size_t idx8(int k, int i, int np) {
+  return ((size_t)(k >> 3) * np + i) * 8 + (k & 7);
+}
+__device__ __forceinline__ size_t idx4(int k, int i, int np) {
+  return ((size_t)(k >> 2) * np + i) * 4 + (k & 3);
+}
+
+// Unwrapped x-cell range [klo, khi] reached from cells xa..xb of a row across
+// the gradient face with image sy (sy = 0: the plain periodic block).
+__device__ __forceinline__ void x_range(const Dev& d, int xa, int xb, int sy, double Delta, double rmarg,
+                                        int& klo, int& khi) {
+  if (sy == 0) {
+    klo = xa - 1; khi = xb + 1;
+  } else {
+    double sh = (double)sy * Delta;
+    klo = (int)floor(((double)xa * d.lx - rmarg - sh) / d.lx);
+    khi = (int)floor(((double)(xb + 1) * d.lx + rmarg - sh) / d.lx);
+  }
+}
+
+__device__ __forceinline__ int cell_of_pos(const Dev& d, double4 p) {
+  return (cell_index(p.z, d.inv_lz, d.nz) * d.ny + cell_index(p.y, d.inv_ly, d.ny)) * d.nx +
+         cell_index(p.x, d.inv_lx, d.nx);
+}
+
+constexpr int kWaves = kTile / 64;
+
+// Tile halo pieces: for each covered row r of the tile, offset (dy, dz) and
+// x-image sx, the slot range of the neighbouring row reached by the tile.
+// Fills the piece tables, assigns LDS offsets in a fixed order while they
+// fit, stages the positions and records halo_slot.  Called by all threads.
+struct Pieces {
+  int start[kMaxRows * 9][kPieces];
+  int count[kMaxRows * 9][kPieces];
+  int off[kMaxRows * 9][kPieces];  // LDS offset, -1 if not staged
+  int sx0[kMaxRows * 9];
+  int npc[kMaxRows * 9];
+  int code[kMaxRows * 9];          // image code (sy, sz) of the row; sx added per piece
+  int s_off[kMaxRows * 9 * kPieces + 1];
+  int s_start[kMaxRows * 9 * kPieces];
+  int s_code[kMaxRows * 9 * kPieces];
+  int nseg, ntot;
+  TileGeom tg;
+};
+
+// Exact list test of one pair: the plain-definition displacement between
+// particle i and slot q under image (sx, sy, sz), r^2 < r_list^2.
+__device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 pj, double shx,
+                                              double shy, double shz, double shd) {
+  double dy = (pi.y - pj.y) - shy;
+  double dx = ((pi.x - pj.x) - shd) - shx;
+  double dz = (pi.z - pj.z) - shz;
+  double r2 = dx * dx + dy * dy;
+  r2 = r2 + dz * dz;
+  return r2 < d.rlist2;
+}
+
+__global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
+  // staged positions: floats relative to the tile's first particle, image
+  // added (8 spare entries: a batch may read up to 7 past the halo)
+  __shared__ float hx[kHalo + 8], hy[kHalo + 8], hz[kHalo + 8];
+  __shared__ Pieces pc;
+  // per-lane ring of list entries, and a spare entry for rejected ones
+  __shared__ __align__(16) uint16_t lbuf[kTile][16];
+  __shared__ uint16_t lspare[kTile];
+  __shared__ int skip;
   Ctrl* c = d.ctrl;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
+  if (threadIdx.x == 0) skip = rebuild_off(d, force) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
   const int np = d.np, K = d.K, n = d.n;
+  const int tile = xcd_block(d.ntiles);
+  const int s0 = tile * kTile;
+  const int i = s0 + threadIdx.x;
+  const bool valid = i < n;
   const int pn = 1 - c->pos_cur, an = 1 - c->aux_cur;
   const double4* P = reinterpret_cast<const double4*>(d.pos[pn]);
   const double Delta = c->Delta;
-  const double4 pi = P[i];
+  const double rmarg = d.rlist * (1.0 + 1e-12) + 1e-12 * (d.Lx + d.Ly + d.Lz);
+  TileGeom& tg = pc.tg;
+
+  // ---- tile geometry
+  if (threadIdx.x == 0) {
+    int last = min(s0 + kTile, n) - 1;
+    int ca = cell_of_pos(d, P[s0]), cb = cell_of_pos(d, P[last]);
+    tg.c_first = ca;
+    tg.c_last = cb;
+    tg.row_first = ca / d.nx;
+    tg.nrows = cb / d.nx - ca / d.nx + 1;
+    tg.staged_ok = tg.nrows <= kMaxRows ? 1 : 0;
+  }
+  __syncthreads();
+  // ---- pieces: one thread per (covered row, dz, dy)
+  const int ncombo = tg.staged_ok ? tg.nrows * 9 : 0;
+  for (int t = threadIdx.x; t < ncombo; t += kTile) {
+    int r = t / 9, rem = t % 9;
+    int dzc = rem / 3 - 1, dyc = rem % 3 - 1;
+    int row = tg.row_first + r;
+    int iy = row % d.ny, iz = row / d.ny;
+    int xa = (r == 0) ? tg.c_first % d.nx : 0;
+    int xb = (r == tg.nrows - 1) ? tg.c_last % d.nx : d.nx - 1;
+    int jz = iz + dzc, sz = jz < 0 ? -1 : (jz >= d.nz ? 1 : 0);
+    jz -= sz * d.nz;
+    int jy = iy + dyc, sy = jy < 0 ? -1 : (jy >= d.ny ? 1 : 0);
+    jy -= sy * d.ny;
+    int klo, khi;
+    x_range(d, xa, xb, sy, Delta, rmarg, klo, khi);
+    int sxa = floor_div(klo, d.nx), sxb = floor_div(khi, d.nx);
+    int npc = sxb - sxa + 1;
+    pc.sx0[t] = sxa;
+    pc.code[t] = (sy + 1) | ((sz + 1) << 2);
+    pc.npc[t] = npc <= kPieces ? npc : 0;  // 0: not staged (too many images)
+    const int rowbase = (jz * d.ny + jy) * d.nx;
+    for (int q = 0; q < kPieces; ++q) {
+      pc.start[t][q] = 0;
+      pc.count[t][q] = 0;
+      if (q < pc.npc[t]) {
+        int sx = sxa + q;
+        int ka = max(klo, sx * d.nx), kb = min(khi, sx * d.nx + d.nx - 1);
+        int c0 = rowbase + (ka - sx * d.nx), c1 = rowbase + (kb - sx * d.nx);
+        pc.start[t][q] = d.cell_start[c0];
+        pc.count[t][q] = d.cell_start[c1 + 1] - d.cell_start[c0];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- LDS offsets in a fixed order (prefix sum over the pieces); pieces that
+  // do not fit stay global
+  {
+    __shared__ int wsum[kWaves];
+    const int npieces = ncombo * kPieces;  // <= kMaxRows * 9 * kPieces <= 2 * kTile
+    int cnt[2], incl[2];
+    int tot_prev = 0;
+    for (int half = 0; half < 2; ++half) {
+      int e = half * kTile + threadIdx.x;
+      int t = e / kPieces, q = e % kPieces;
+      cnt[half] = (e < npieces && q < pc.npc[t]) ? pc.count[t][q] : 0;
+      // block inclusive scan of cnt[half]
+      int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      int v = cnt[half];
+      for (int o = 1; o < 64; o <<= 1) {
+        int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+      }
+      if (lane == 63) wsum[wv] = v;
+      __syncthreads();
+      int woff = 0, wtot = 0;
+      for (int w2 = 0; w2 < kWaves; ++w2) { if (w2 < wv) woff += wsum[w2]; wtot += wsum[w2]; }
+      incl[half] = tot_prev + woff + v;
+      tot_prev += wtot;
+      __syncthreads();
+    }
+    // a piece is staged iff it ends within the halo; the staged set is a prefix
+    for (int half = 0; half < 2; ++half) {
+      int e = half * kTile + threadIdx.x;
+      if (e < npieces) {
+        int t = e / kPieces, q = e % kPieces;
+        bool real = q < pc.npc[t];
+        int start_off = incl[half] - cnt[half];
+        pc.off[t][q] = (real && incl[half] <= kHalo) ? start_off : -1;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int ns = 0, off = 0;
+      for (int e = 0; e < npieces; ++e) {
+        int t = e / kPieces, q = e % kPieces;
+        if (pc.off[t][q] < 0) continue;
+        if (pc.count[t][q] > 0) {
+          pc.s_off[ns] = pc.off[t][q];
+          pc.s_start[ns] = pc.start[t][q];
+          pc.s_code[ns] = pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1);
+          ++ns;
+        }
+        off = pc.off[t][q] + pc.count[t][q];
+      }
+      pc.s_off[ns] = off;
+      pc.nseg = ns;
+      pc.ntot = off;
+      d.tile_nstage[tile] = off;
+    }
+  }
+  __syncthreads();
+  // ---- stage positions and record their slots (flat, four loads in flight)
+  const double4 org = P[s0];
+  {
+    const int tot = pc.ntot, nseg = pc.nseg;
+    for (int h0 = threadIdx.x; h0 < tot; h0 += 4 * kTile) {
+      int slot[4], code[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int h = h0 + u * kTile;
+        slot[u] = n;
+        code[u] = 0;
+        if (h < tot) {
+          int lo = 0, hi = nseg - 1;  // last segment with s_off <= h
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (pc.s_off[mid] <= h) lo = mid; else hi = mid - 1;
+          }
+          slot[u] = pc.s_start[lo] + (h - pc.s_off[lo]);
+          code[u] = pc.s_code[lo];
+        }
+      }
+      double4 pj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pj[u] = P[slot[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int h = h0 + u * kTile;
+        if (h < tot) {
+          int sx, sy, sz;
+          unpack_img((uint8_t)code[u], sx, sy, sz);
+          hx[h] = (float)((pj[u].x + ((double)sy * Delta + (double)sx * d.Lx)) - org.x);
+          hy[h] = (float)((pj[u].y + (double)sy * d.Ly) - org.y);
+          hz[h] = (float)((pj[u].z + (double)sz * d.Lz) - org.z);
+          d.halo_slot[(size_t)tile * kHalo + h] = slot[u];
+          d.halo_code[(size_t)tile * kHalo + h] = (uint8_t)code[u];
+        }
+      }
+    }
+  }
+
+  __syncthreads();
+
+  // ---- scan: each lane walks its own stencil.  For each (dy, dz) the x-cells
+  // the particle reaches in that row form one contiguous LDS range (the row's
+  // x-image pieces are staged back to back, images already added), so a lane
+  // tests [a, b) with eight candidates per batch; the wave runs to its
+  // longest range.  Lanes whose row was not staged walk the cells in global
+  // memory with the exact test instead.
+  const double4 pi = P[valid ? i : s0];
+  const float pix = (float)(pi.x - org.x), piy = (float)(pi.y - org.y), piz = (float)(pi.z - org.z);
   const int ix = cell_index(pi.x, d.inv_lx, d.nx);
   const int iy = cell_index(pi.y, d.inv_ly, d.ny);
   const int iz = cell_index(pi.z, d.inv_lz, d.nz);
-  const double rl2 = d.rlist2;
-  const double rmarg = d.rlist * (1.0 + 1e-12) + 1e-12 * (d.Lx + d.Ly + d.Lz);
-  int npl = 0, nim = 0;
-  for (int dzc = -1; dzc <= 1; ++dzc) {
-    int jz = iz + dzc;
-    int sz = jz < 0 ? -1 : (jz >= d.nz ? 1 : 0);
+  const int rt = (iz * d.ny + iy) - tg.row_first;  // tile row of the particle
+  const bool row_staged = valid && tg.staged_ok && rt >= 0 && rt < tg.nrows;
+  int self_h = -1;  // LDS position of the particle itself (plain image)
+  if (row_staged) {
+    const int t = rt * 9 + 4;  // dz = dy = 0
+    const int q = -pc.sx0[t];  // sx = 0
+    if (q >= 0 && q < pc.npc[t] && pc.off[t][q] >= 0) self_h = i - pc.start[t][q] + pc.off[t][q];
+  }
+  const float tlo = d.nb_lo, thi = d.nb_hi;
+  const size_t hbase = (size_t)tile * kHalo;
+  int npl = 0, nog = 0;
+  for (int c9 = 0; c9 < 9; ++c9) {
+    const int dzc = c9 / 3 - 1, dyc = c9 % 3 - 1;
+    int jz = iz + dzc, sz = jz < 0 ? -1 : (jz >= d.nz ? 1 : 0);
     jz -= sz * d.nz;
-    for (int dyc = -1; dyc <= 1; ++dyc) {
-      int jy = iy + dyc;
-      int sy = jy < 0 ? -1 : (jy >= d.ny ? 1 : 0);
-      jy -= sy * d.ny;
-      int klo, khi;
-      if (sy == 0) {
-        klo = ix - 1; khi = ix + 1;
-      } else {
-        double sh = (double)sy * Delta;
-        klo = (int)floor(((double)ix * d.lx - rmarg - sh) / d.lx);
-        khi = (int)floor(((double)(ix + 1) * d.lx + rmarg - sh) / d.lx);
+    int jy = iy + dyc, sy = jy < 0 ? -1 : (jy >= d.ny ? 1 : 0);
+    jy -= sy * d.ny;
+    int klo, khi;
+    x_range(d, ix, ix, sy, Delta, rmarg, klo, khi);
+    const int rowbase = (jz * d.ny + jy) * d.nx;
+    int a = 0, b = 0;
+    bool walk_global = valid;
+    if (row_staged) {
+      const int t = rt * 9 + c9;
+      const int sxa = floor_div(klo, d.nx), sxb = floor_div(khi, d.nx);
+      const int qa = sxa - pc.sx0[t], qb = sxb - pc.sx0[t];
+      // staged pieces form a prefix, so the last one staged implies the rest
+      if (qa >= 0 && qb < pc.npc[t] && pc.off[t][qb] >= 0) {
+        a = d.cell_start[rowbase + (klo - sxa * d.nx)] + (pc.off[t][qa] - pc.start[t][qa]);
+        b = d.cell_start[rowbase + (khi - sxb * d.nx) + 1] + (pc.off[t][qb] - pc.start[t][qb]);
+        walk_global = false;
       }
-      const int rowbase = (jz * d.ny + jy) * d.nx;
-      const double shy = (double)sy * d.Ly;
-      const double shd = (double)sy * Delta;
-      const double shz = (double)sz * d.Lz;
-      int k = klo;
-      while (k <= khi) {
-        // one segment: cells k .. kend with the same x image
-        int sx = floor_div(k, d.nx);
-        int kend = (sx + 1) * d.nx - 1;
-        if (kend > khi) kend = khi;
-        const int c0 = rowbase + (k - sx * d.nx);
-        const int c1 = rowbase + (kend - sx * d.nx);
-        const int q0 = d.cell_start[c0], q1 = d.cell_start[c1 + 1];
+    }
+    int wlen = b - a;
+    for (int o = 32; o > 0; o >>= 1) wlen = max(wlen, __shfl_xor(wlen, o, 64));
+    wlen = __builtin_amdgcn_readfirstlane(wlen);
+    const int sq = (c9 == 4) ? self_h : -1;
+    for (int j0 = 0; j0 < wlen; j0 += 8) {
+      const int h0 = a + j0;
+      // candidates past the lane's range are read (in bounds) and masked off
+      const int lim = b - h0;
+      unsigned keep = lim >= 8 ? 0xffu : (lim > 0 ? (1u << lim) - 1u : 0u);
+      if (sq >= h0 && sq < h0 + 8) keep &= ~(1u << (sq - h0));
+      const int hc = min(h0, kHalo);
+      unsigned m_in = 0u, m_band = 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float dx = pix - hx[hc + u];
+        const float dy = piy - hy[hc + u];
+        const float dz = piz - hz[hc + u];
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+        m_in |= (r2 < tlo ? 1u : 0u) << u;
+        m_band |= (r2 < thi ? 1u : 0u) << u;
+      }
+      m_in &= keep;
+      m_band &= keep & ~m_in;
+      while (m_band) {  // rare: FP32 r^2 within the rounding band of r_list^2
+        const int u = __builtin_ctz(m_band);
+        m_band &= m_band - 1u;
+        const int h = h0 + u;
+        int sx2, sy2, sz2;
+        unpack_img(d.halo_code[hbase + h], sx2, sy2, sz2);
+        if (in_list_exact(d, pi, P[d.halo_slot[hbase + h]], (double)sx2 * d.Lx, (double)sy2 * d.Ly,
+                          (double)sz2 * d.Lz, (double)sy2 * Delta))
+          m_in |= 1u << u;
+      }
+      // append the accepted LDS indices into a ring of 16 per lane (rejected
+      // ones go to the spare entry); a completed block of 8 leaves as one
+      // 16-byte store
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int pos = (npl + __builtin_popcount(m_in & ((1u << u) - 1u))) & 15;
+        uint16_t* dst = ((m_in >> u) & 1u) ? &lbuf[threadIdx.x][pos] : &lspare[threadIdx.x];
+        *dst = (uint16_t)(h0 + u);
+      }
+      const int nn = npl + __builtin_popcount(m_in);
+      if ((nn >> 3) != (npl >> 3)) {
+        const int blk = npl >> 3;
+        if ((blk + 1) * 8 <= K)
+          reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np + i] =
+              *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
+      }
+      npl = nn;
+    }
+    if (walk_global) {
+      // this particle's cells of the row, read from global memory
+      for (int k = klo; k <= khi; ++k) {
+        const int sx = floor_div(k, d.nx);
+        const int cell = rowbase + (k - sx * d.nx);
         const bool plain = (sx == 0 && sy == 0 && sz == 0);
-        const double shx = (double)sx * d.Lx;
         const uint8_t code = pack_img(sx, sy, sz);
-        for (int q = q0; q < q1; q += 4) {
-          int qq[4];
-          double4 pj[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            qq[u] = (q + u < q1) ? q + u : n;
-            pj[u] = P[qq[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            double dy = (pi.y - pj[u].y) - shy;
-            double dx = ((pi.x - pj[u].x) - shd) - shx;
-            double dz = (pi.z - pj[u].z) - shz;
-            double r2 = dx * dx + dy * dy;
-            r2 = r2 + dz * dz;
-            if (r2 < rl2 && !(plain && qq[u] == i)) {
-              if (npl + nim < K) {
-                if (plain) {
-                  d.nl[npl * np + i] = qq[u];
-                } else {
-                  int row = K - 1 - nim;
-                  d.nl[row * np + i] = qq[u];
-                  d.nlc[row * np + i] = code;
-                }
-              }
-              if (plain) ++npl; else ++nim;
-            }
+        for (int q = d.cell_start[cell]; q < d.cell_start[cell + 1]; ++q) {
+          if (plain && q == i) continue;
+          if (in_list_exact(d, pi, P[q], (double)sx * d.Lx, (double)sy * d.Ly, (double)sz * d.Lz,
+                            (double)sy * Delta)) {
+            if (nog < K) { d.nlo[idx4(nog, i, np)] = (uint32_t)q; d.nlc[idx4(nog, i, np)] = code; }
+            ++nog;
           }
         }
-        k = kend + 1;
       }
     }
   }
-  atomicMax(&c->max_nb, npl + nim);
-  // pad both parts to whole batches with the sentinel
+  {  // telemetry: one atomic per wave
+    int mx = npl + nog;
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&c->max_nb, mx);
+  }
+  if (!valid) return;
   int npl_p = (npl + kPlainBatch - 1) / kPlainBatch * kPlainBatch;
-  int nim_p = (nim + kImgBatch - 1) / kImgBatch * kImgBatch;
-  if (npl_p + nim_p > K) {
+  int nog_p = (nog + kOtherBatch - 1) / kOtherBatch * kOtherBatch;
+  if (npl_p > K || nog_p > K) {
     latch(c, LE_E_CAPACITY);
-    npl_p = 0;
-    nim_p = 0;
+    npl_p = nog_p = 0;
   } else {
-    for (int r = npl; r < npl_p; ++r) d.nl[r * np + i] = n;
-    const uint8_t zero = pack_img(0, 0, 0);
-    for (int r = nim; r < nim_p; ++r) {
-      d.nl[(K - 1 - r) * np + i] = n;
-      d.nlc[(K - 1 - r) * np + i] = zero;
+    if (npl < npl_p) {  // pad and flush the partial block
+      const int blk = npl >> 3;
+      for (int r = npl; r < npl_p; ++r) lbuf[threadIdx.x][r & 15] = (uint16_t)kHalo;
+      reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np + i] =
+          *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
     }
+    const uint8_t zero = pack_img(0, 0, 0);
+    for (int r = nog; r < nog_p; ++r) { d.nlo[idx4(r, i, np)] = (uint32_t)n; d.nlc[idx4(r, i, np)] = zero; }
   }
   d.n_plain[i] = npl_p;
-  d.n_img[i] = nim_p;
+  d.n_og[i] = nog_p;
   if (d.chain_len > 0) {
-    int t = d.tag[an][i];
+    int tg_ = d.tag[an][i];
     int lo = -1, hi = -1;
-    if (t < d.n_bonded) {
-      int kk = t % d.chain_len;
-      if (kk > 0) lo = d.slot_of_tag[t - 1];
-      if (kk < d.chain_len - 1) hi = d.slot_of_tag[t + 1];
+    if (tg_ < d.n_bonded) {
+      int kk = tg_ % d.chain_len;
+      if (kk > 0) lo = d.slot_of_tag[tg_ - 1];
+      if (kk < d.chain_len - 1) hi = d.slot_of_tag[tg_ + 1];
     }
     d.bond[i] = lo;
     d.bond[np + i] = hi;
@@ -432,22 +704,6 @@ __device__ void control_update(const Dev& d, Ctrl* c) {
   if (d.rlist <= rc || need >= d.rlist * (1.0 - 1e-9)) c->rebuild = 1;
 }
 
-// Last-block pattern: every block publishes its writes and takes a ticket;
-// the block that takes the final ticket sees all of them.  Returns true in
-// every thread of that block.
-__device__ __forceinline__ bool last_block(Ctrl* c) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(&c->ticket, 1u);
-    is_last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
 // Sum the per-block stress partials (fixed order) and write the stress
 // -(K + W)/V, or with virial_only the pair virial W, into out6.  Called by one
 // whole block.
@@ -456,7 +712,7 @@ __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
   double acc[kStressComps];
 #pragma unroll
   for (int k = 0; k < kStressComps; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < d.nblocks; b += kBlock) {
+  for (int b = threadIdx.x; b < d.nblocks; b += blockDim.x) {
 #pragma unroll
     for (int k = 0; k < kStressComps; ++k) acc[k] += d.partials[b * kStressComps + k];
   }
@@ -470,7 +726,7 @@ __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
   __syncthreads();
   if (threadIdx.x < 6) {
     double kin = 0.0, vir = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
       kin += red[w][threadIdx.x];
       vir += red[w][6 + threadIdx.x];
     }
@@ -510,45 +766,58 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(c, LE_E_NONFINITE);
   }
   vmax_commit(c, v2);
-  if (last_block(c) && threadIdx.x == 0) {
-    control_update(d, c);
-    c->ticket = 0u;
-  }
+}
+
+// One thread: advance the step after a drift (see control_update).
+__global__ void k_control(Dev d) {
+  Ctrl* c = d.ctrl;
+  if (c->status) return;
+  control_update(d, c);
 }
 
 // ---------------------------------------------------------- force kernel
 template <bool VIR>
 __device__ __forceinline__ void add_pair(double f, double dx, double dy, double dz, double& fx,
                                          double& fy, double& fz, double* w) {
-  double ax = f * dx, ay = f * dy, az = f * dz;
-  fx += ax; fy += ay; fz += az;
+  fx = fma(f, dx, fx); fy = fma(f, dy, fy); fz = fma(f, dz, fz);
   if (VIR) {
+    double ax = f * dx, ay = f * dy, az = f * dz;
     w[0] = fma(dx, ax, w[0]); w[1] = fma(dy, ay, w[1]); w[2] = fma(dz, az, w[2]);
     w[3] = fma(dx, ay, w[3]); w[4] = fma(dx, az, w[4]); w[5] = fma(dy, az, w[5]);
   }
 }
 
+// Scalar LJ force factor f (force on i = f d) for r^2 = r2, zero outside the
+// cutoff.  Branch-free so that the candidates of one batch are independent
+// instruction streams the compiler can interleave.
 template <bool MIXED>
-__device__ __forceinline__ double lj_scalar(double r2, double sig2, double eps24) {
+__device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, double eps24) {
+  const bool in = r2 < rc2;
   if (MIXED) {
     float r2f = (float)r2;
     float inv = __builtin_amdgcn_rcpf(r2f);
     inv = inv * (2.0f - r2f * inv);  // one Newton step: ~1 ulp
     float s2 = (float)sig2 * inv;
     float s6 = s2 * s2 * s2;
-    return (double)((float)eps24 * s6 * (2.0f * s6 - 1.0f) * inv);
+    float f = (float)eps24 * s6 * (2.0f * s6 - 1.0f) * inv;
+    return in ? (double)f : 0.0;
   } else {
-    double inv = 1.0 / r2;
+    double inv = __builtin_amdgcn_rcp(r2);
+    double e = fma(-r2, inv, 1.0);
+    inv = fma(inv, e, inv);
+    e = fma(-r2, inv, 1.0);
+    inv = fma(inv, e, inv);
     double s2 = sig2 * inv;
     double s6 = s2 * s2 * s2;
-    return eps24 * s6 * fma(2.0, s6, -1.0) * inv;
+    double f = eps24 * s6 * fma(2.0, s6, -1.0) * inv;
+    return in ? f : 0.0;
   }
 }
 
 // Block reduction of 12 per-thread sums into partials[block][12] (fixed
 // order: wave butterflies, then waves in index order).
 __device__ __forceinline__ void block_partials(double* vals, double* out, int lb) {
-  __shared__ double red[kBlock / 64][kStressComps];
+  __shared__ double red[kBlock / 64][kStressComps];  // blockDim.x <= kBlock
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kStressComps; ++k) {
@@ -559,7 +828,7 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
   __syncthreads();
   if (threadIdx.x < kStressComps) {
     double s = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += red[w][threadIdx.x];
     out[lb * kStressComps + threadIdx.x] = s;
   }
 }
@@ -573,75 +842,121 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE>
-__global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_out,
-                                                  double* __restrict__ sample_out) {
+__global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_out,
+                                                 double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
+  __shared__ double hx[kHalo + 1], hy[kHalo + 1], hz[kHalo + 1];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = c->status;
   __syncthreads();
   if (skip) return;
-  const int lb = xcd_block(d.nblocks);
-  const int i = lb * kBlock + threadIdx.x;
+  const int lb = xcd_block(d.ntiles);
+  const int i = lb * kTile + threadIdx.x;
   const bool valid = i < d.n;
-  const int np = d.np, K = d.K;
+  const int np = d.np;
   const int pc = c->pos_cur, ac = c->aux_cur;
   const double Delta = c->Delta;
   const int W = c->wraps;
   const double4* P = reinterpret_cast<const double4*>(d.pos[pc]);
+  // Stage the tile's halo: the slots recorded at the last build with their
+  // current positions, each shifted by its periodic / Lees-Edwards image
+  // (sy Delta + sx L_x, sy L_y, sz L_z; the x image absorbs the offset's
+  // wraps since the build).  A partner's displacement is then x_i - x_h.  All
+  // slot loads, then all position loads, are in flight together.
+  {
+    const int nst = d.tile_nstage[lb];
+    const int* hs = d.halo_slot + (size_t)lb * kHalo;
+    const uint8_t* hc = d.halo_code + (size_t)lb * kHalo;
+    constexpr int U = kHalo / kTile;
+    int slot[U];
+    uint8_t code[U];
+    const int nsent = d.n;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // always load from an index inside this tile's table, then select the value
+      int h = threadIdx.x + u * kTile;
+      int hh = h < nst ? h : 0;
+      int sv = hs[hh];
+      uint8_t cv = hc[hh];
+      slot[u] = (h < nst) ? sv : nsent;
+      code[u] = (h < nst) ? cv : pack_img(0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int h = threadIdx.x + u * kTile;
+      double4 pj = P[slot[u]];
+      int sx, sy, sz;
+      unpack_img(code[u], sx, sy, sz);
+      sx += sy * W;
+      if (h < nst) {
+        hx[h] = pj.x + ((double)sy * Delta + (double)sx * d.Lx);
+        hy[h] = pj.y + (double)sy * d.Ly;
+        hz[h] = pj.z + (double)sz * d.Lz;
+      }
+    }
+    if (threadIdx.x == 0) { hx[kHalo] = 1e100; hy[kHalo] = 1e100; hz[kHalo] = 1e100; }
+  }
+  __syncthreads();
   double fx = 0.0, fy = 0.0, fz = 0.0;
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
   if (valid) {
     pi = P[i];
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
-    const int npl = d.n_plain[i];  // a multiple of kPlainBatch (sentinel-padded)
-    const int* __restrict__ nl = d.nl + i;
-    int jn[kPlainBatch];
-    if (npl > 0) {
+    // staged partners (already shifted to their image): one 16-byte index load
+    // per batch of 8, two batches ahead
+    const int nb = d.n_plain[i] / kPlainBatch;
+    const uint4* __restrict__ l8 = reinterpret_cast<const uint4*>(d.nl16) + i;
+    const uint4 zero4 = make_uint4(kHalo | (kHalo << 16), kHalo | (kHalo << 16), kHalo | (kHalo << 16),
+                                   kHalo | (kHalo << 16));
+    // loads always read an existing block of the list array and the value is
+    // selected afterwards (a select between pointers would become a flat load)
+    const int last_blk = d.K / kPlainBatch - 1;
+    uint4 t0 = l8[0];
+    uint4 t1 = l8[(size_t)min(1, last_blk) * np];
+    uint4 v0 = nb > 0 ? t0 : zero4;
+    uint4 v1 = nb > 1 ? t1 : zero4;
+    for (int b = 0; b < nb; ++b) {
+      uint4 t2 = l8[(size_t)min(b + 2, last_blk) * np];
+      uint4 v2 = (b + 2 < nb) ? t2 : zero4;
+      int j[8] = {(int)(v0.x & 0xffff), (int)(v0.x >> 16), (int)(v0.y & 0xffff), (int)(v0.y >> 16),
+                  (int)(v0.z & 0xffff), (int)(v0.z >> 16), (int)(v0.w & 0xffff), (int)(v0.w >> 16)};
+      double xj[8], yj[8], zj[8];
 #pragma unroll
-      for (int u = 0; u < kPlainBatch; ++u) jn[u] = nl[u * np];
-    }
-    for (int k = 0; k < npl; k += kPlainBatch) {
-      double4 pj[kPlainBatch];
+      for (int u = 0; u < 8; ++u) { xj[u] = hx[j[u]]; yj[u] = hy[j[u]]; zj[u] = hz[j[u]]; }
 #pragma unroll
-      for (int u = 0; u < kPlainBatch; ++u) pj[u] = P[jn[u]];
-      if (k + kPlainBatch < npl) {
-#pragma unroll
-        for (int u = 0; u < kPlainBatch; ++u) jn[u] = nl[(k + kPlainBatch + u) * np];
-      }
-#pragma unroll
-      for (int u = 0; u < kPlainBatch; ++u) {
-        double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
+      for (int u = 0; u < 8; ++u) {
+        double dx = pi.x - xj[u], dy = pi.y - yj[u], dz = pi.z - zj[u];
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
-        if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+        add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
       }
+      v0 = v1;
+      v1 = v2;
     }
-    const int nim = d.n_img[i];  // a multiple of kImgBatch
-    for (int k = 0; k < nim; k += kImgBatch) {
-      int jj[kImgBatch];
-      uint8_t cc[kImgBatch];
-      double4 pj[kImgBatch];
+    // partners that were not staged: global memory, exact image arithmetic
+    const int nog = d.n_og[i];
+    const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo) + i;
+    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc) + i;
+    for (int k = 0; k < nog; k += kOtherBatch) {
+      uint4 jv = l4[(size_t)(k / kOtherBatch) * np];
+      uint32_t cv = c4[(size_t)(k / kOtherBatch) * np];
+      uint32_t jj[4] = {jv.x, jv.y, jv.z, jv.w};
+      double4 pj[4];
 #pragma unroll
-      for (int u = 0; u < kImgBatch; ++u) {
-        int row = K - 1 - (k + u);
-        jj[u] = nl[row * np];
-        cc[u] = d.nlc[row * np + i];
-      }
+      for (int u = 0; u < 4; ++u) pj[u] = P[jj[u]];
 #pragma unroll
-      for (int u = 0; u < kImgBatch; ++u) pj[u] = P[jj[u]];
-#pragma unroll
-      for (int u = 0; u < kImgBatch; ++u) {
+      for (int u = 0; u < 4; ++u) {
         int sx, sy, sz;
-        unpack_img(cc[u], sx, sy, sz);
+        unpack_img((uint8_t)(cv >> (8 * u)), sx, sy, sz);
         sx += sy * W;
         double dy = (pi.y - pj[u].y) - (double)sy * d.Ly;
         double dx = ((pi.x - pj[u].x) - (double)sy * Delta) - (double)sx * d.Lx;
         double dz = (pi.z - pj[u].z) - (double)sz * d.Lz;
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
-        if (r2 < rc2) add_pair<VIR>(lj_scalar<MIXED>(r2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+        add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
       }
     }
     if (BONDS) {
@@ -731,15 +1046,6 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev d, double* __restrict__ f_
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.5 * w[k]; }
     block_partials(vals, d.partials, lb);
   }
-  if (MODE == kStepFused || (MODE == kStepLast && SAMPLE)) {
-    if (last_block(c)) {
-      if (SAMPLE) reduce_partials(d, sample_out, false);
-      if (threadIdx.x == 0) {
-        if (MODE == kStepFused) control_update(d, c);
-        c->ticket = 0u;
-      }
-    }
-  }
 }
 
 // Stand-alone reduction of the block partials (le_forces, le_stress).
@@ -776,13 +1082,22 @@ __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long lo
   if (d.ctrl->status) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  const int np = d.np, K = d.K;
+  const int np = d.np;
   const int32_t* tag = d.tag[d.ctrl->aux_cur];
-  int ti = tag[i];
-  int npl = d.n_plain[i], nim = d.n_img[i];
-  for (int k = 0; k < npl + nim; ++k) {
-    int row = k < npl ? k : K - 1 - (k - npl);
-    int tj = tag[d.nl[row * np + i]];
+  const int* hs = d.halo_slot + (size_t)(i / kTile) * kHalo;
+  const int ti = tag[i];
+  const int npl = d.n_plain[i], nog = d.n_og[i];
+  for (int k = 0; k < npl + nog; ++k) {
+    int slot;
+    if (k < npl) {
+      int h = d.nl16[idx8(k, i, np)];
+      if (h == kHalo) continue;
+      slot = hs[h];
+    } else {
+      slot = (int)d.nlo[idx4(k - npl, i, np)];
+      if (slot == d.n) continue;
+    }
+    int tj = tag[slot];
     if (ti < tj) {
       unsigned long long idx = atomicAdd(counter, 1ull);
       if ((int64_t)idx < cap) { pairs[2 * idx] = ti; pairs[2 * idx + 1] = tj; }
@@ -823,8 +1138,13 @@ hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force) {
   hipLaunchKernelGGL(k_scan_add, dim3(nchunks), dim3(kBlock), 0, s, d, f, nchunks);
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, d, f);
   hipLaunchKernelGGL(k_rank_permute, dim3(nb), dim3(kBlock), 0, s, d, f);
-  hipLaunchKernelGGL(k_neighbors, dim3(nb), dim3(kBlock), 0, s, d, f);
+  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(kTile), 0, s, d, f);
   hipLaunchKernelGGL(k_rebuild_finish, dim3(1), dim3(1), 0, s, d, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_control(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, d);
   return hipGetLastError();
 }
 
@@ -835,7 +1155,7 @@ hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
 
 template <int MODE, bool SAMPLE>
 static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so) {
-  dim3 g(d.nblocks), b(kBlock);
+  dim3 g(d.ntiles), b(kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
