@@ -83,6 +83,19 @@ def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=Tru
     return out
 
 
+def copy_probe(mib=1024, reps=5):
+    """Plain device-to-device copy of a known size (calibrates HBM byte counters)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}),
+          flush=True)
+
+
 def cpu_baseline(n, shear_rate, nsteps):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
@@ -112,6 +125,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events in the timed region (then no per-kernel roofline)")
+    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -120,10 +136,13 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe()
+        return
     log(f"bench: LJ n={args.n} shear_rate={args.shear_rate} {args.precision} "
         f"steps={args.steps} warmup={args.warmup}")
     r = run_gpu(args.n, args.shear_rate, args.precision, args.steps, args.warmup,
-                timing=not args.no_timing)
+                timing=not args.no_timing, skin=args.skin)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, phases={r['phases']}")
 
@@ -144,12 +163,12 @@ def main():
     extra = {}
     if not args.no_extra:
         for sr in (0.01, 1.0):
-            e = run_gpu(args.n, sr, args.precision, 2000, 100)
+            e = run_gpu(args.n, sr, args.precision, 2000, 100, skin=args.skin)
             extra[f"shear_rate_{sr}"] = dict(value=e["value"], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
                                              eta=e["eta"])
             log(f"bench: shear_rate={sr}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
         other = "mixed" if args.precision == "fp64" else "fp64"
-        m = run_gpu(args.n, args.shear_rate, other, 2000, 100)
+        m = run_gpu(args.n, args.shear_rate, other, 2000, 100, skin=args.skin)
         extra[f"{other}_value"] = m["value"]
         fm, fn = m["phases"]["force"]
         extra[f"{other}_force_kernel_us"] = 1e3 * fm / max(fn, 1)
@@ -176,11 +195,12 @@ def main():
         "config": {
             "workload": f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
                         f"T=1, Langevin gamma=1 on peculiar velocity, shear_rate={args.shear_rate}, "
-                        f"dt=0.005, skin 0.3, {args.precision}",
+                        f"dt=0.005, skin {args.skin}, {args.precision}",
             "n_particles": r["n"],
             "shear_rate": args.shear_rate,
             "precision": args.precision,
             "stress_sample_every": 10,
+            "skin": args.skin,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

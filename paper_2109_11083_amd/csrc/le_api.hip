@@ -16,6 +16,7 @@ struct le_sim {
   Dev d;
   hipStream_t stream;
   int32_t host_status;                 // last status seen by a synchronising call
+  Ctrl* ctrl_base;                     // the two control copies; d.ctrl is the current one
   unsigned long long* counter;         // device scratch counter (pairs_out)
   double* scratch6;                    // device 6 doubles
   // phase timing (le_timing_enable)
@@ -39,6 +40,7 @@ struct Geometry {
   int32_t K;
   int64_t np;
   int32_t nblocks;
+  int32_t bcap;
 };
 
 le_status validate(const le_params* p, Geometry* g) {
@@ -80,6 +82,12 @@ le_status validate(const le_params* p, Geometry* g) {
   if (g->K > 4096) g->K = 4096;
   g->K = (g->K + 7) / 8 * 8;  // lists are stored in blocks of 8 (plain) and 4 (other) entries
   g->np = (p->n + 1 + kBlock - 1) / kBlock * kBlock;  // +1: sentinel slot
+  {
+    // bucket capacity: generous over the mean cell occupancy
+    double mean = (double)p->n / ((double)g->nc[0] * g->nc[1] * g->nc[2]);
+    double cap = fmin(4.0 * mean + 32.0, (double)p->n);
+    g->bcap = ((int32_t)ceil(cap) + 7) / 8 * 8;
+  }
   g->nblocks = (int32_t)((p->n + kTile - 1) / kTile);
   return LE_OK;
 }
@@ -94,10 +102,10 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   };
   const size_t np = (size_t)g.np;
   const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
-  const size_t nchunks = (ncell + kScanChunk - 1) / kScanChunk;
   Dev t;
   memset(&t, 0, sizeof(t));
-  t.ctrl = (Ctrl*)take(sizeof(Ctrl));
+  t.ctrl = (Ctrl*)take(2 * sizeof(Ctrl));
+  t.flags = (Flags*)take(sizeof(Flags));
   for (int b = 0; b < 2; ++b) {
     t.pos[b] = (double*)take(4 * np * sizeof(double));
     t.vel[b] = (double*)take(3 * np * sizeof(double));
@@ -107,10 +115,9 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.slot_of_tag = (int32_t*)take(np * sizeof(int32_t));
   t.cell_of = (int32_t*)take(np * sizeof(int32_t));
   t.rank = (int32_t*)take(np * sizeof(int32_t));
-  t.src = (int32_t*)take(np * sizeof(int32_t));
+  t.bucket = (int32_t*)take(ncell * (size_t)g.bcap * sizeof(int32_t));
   t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
-  t.block_sums = (int32_t*)take(nchunks * sizeof(int32_t));
   t.nl16 = (uint16_t*)take((size_t)g.K * np * sizeof(uint16_t));
   t.nlo = (uint32_t*)take((size_t)g.K * np * sizeof(uint32_t));
   t.nlc = (uint8_t*)take((size_t)g.K * np);
@@ -126,18 +133,19 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   if (d) {
     // copy buffer pointers into d (geometry fields are filled by the caller)
     d->ctrl = t.ctrl;
+    d->flags = t.flags;
     for (int b = 0; b < 2; ++b) {
       d->pos[b] = t.pos[b]; d->vel[b] = t.vel[b]; d->frc[b] = t.frc[b]; d->tag[b] = t.tag[b];
     }
-    d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->src = t.src;
-    d->cell_count = t.cell_count; d->cell_start = t.cell_start; d->block_sums = t.block_sums;
+    d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->bucket = t.bucket;
+    d->cell_count = t.cell_count; d->cell_start = t.cell_start;
     d->nl16 = t.nl16; d->nlo = t.nlo; d->nlc = t.nlc;
     d->n_plain = t.n_plain; d->n_og = t.n_og;
     d->halo_slot = t.halo_slot; d->halo_code = t.halo_code; d->tile_nstage = t.tile_nstage;
     d->bond = t.bond;
     d->partials = t.partials;
   }
-  if (s) { s->counter = counter; s->scratch6 = scratch6; }
+  if (s) { s->counter = counter; s->scratch6 = scratch6; s->ctrl_base = t.ctrl; }
   return off + kAlign;  // room to align the caller's base pointer
 }
 
@@ -192,6 +200,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->seed_hi = (uint32_t)(p->seed >> 32);
   d->nblocks = g.nblocks;
   d->ntiles = g.nblocks;
+  d->bcap = g.bcap;
 }
 
 le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
@@ -235,10 +244,18 @@ void end_phase(le_sim* s, long k) {
   if (hipEventRecord(s->ev[2 * k + 1], s->stream) == hipSuccess) s->ev_used = (size_t)k + 1;
 }
 
+// Rebuild chain; afterwards the other control copy is the current one.
+le_status rebuild(le_sim* s, bool force, bool control) {
+  Ctrl* next = (s->d.ctrl == s->ctrl_base) ? s->ctrl_base + 1 : s->ctrl_base;
+  le_status st = hip_check(launch_rebuild(s->d, next, s->stream, force, control));
+  s->d.ctrl = next;
+  return st;
+}
+
 le_status read_status(le_sim* s) {
   int32_t st = 0;
   if (hipStreamSynchronize(s->stream) != hipSuccess) return LE_E_HIP;
-  if (hipMemcpy(&st, &s->d.ctrl->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(&st, &s->d.flags->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
     return LE_E_HIP;
   if (st != 0) s->host_status = st;
   return s->host_status;
@@ -280,7 +297,7 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   fill_geometry(p, g, &s->d);
   double Delta0 = le_offset(step0, p->dt, s->d.sv, p->box[0]);
   st = hip_check(launch_load_state(s->d, s->stream, x0, u0, f0, step0, Delta0));
-  if (st == LE_OK) st = hip_check(launch_rebuild(s->d, s->stream, true));
+  if (st == LE_OK) st = rebuild(s, true, false);
   if (st == LE_OK && !f0) st = hip_check(launch_force(s->d, s->stream, kInitForce, false, nullptr, nullptr));
   if (st != LE_OK) {
     delete s;
@@ -294,7 +311,7 @@ le_status le_build_cells(le_sim* s, int32_t* cell_of, int32_t* order, int64_t* p
                          int64_t pairs_cap, int64_t* n_pairs) {
   if (!s) return LE_E_ARG;
   if (s->host_status) return s->host_status;
-  le_status st = hip_check(launch_rebuild(s->d, s->stream, true));
+  le_status st = rebuild(s, true, false);
   if (st == LE_OK && (cell_of || order))
     st = hip_check(launch_state_out(s->d, s->stream, nullptr, nullptr, cell_of, order));
   if (st == LE_OK && (pairs || n_pairs)) {
@@ -338,10 +355,9 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   hipStream_t q = s->stream;
   long ev = begin_phase(s, 2);
   le_status st = hip_check(launch_kick_drift(d, q));
-  if (st == LE_OK) st = hip_check(launch_control(d, q));
   end_phase(s, ev);
   ev = begin_phase(s, 1);
-  if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+  if (st == LE_OK) st = rebuild(s, false, true);
   end_phase(s, ev);
   int64_t ns = 0;
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
@@ -358,11 +374,8 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
       end_phase(s, ev);
     }
     if (st == LE_OK && !last) {
-      ev = begin_phase(s, 2);
-      st = hip_check(launch_control(d, q));
-      end_phase(s, ev);
       ev = begin_phase(s, 1);
-      if (st == LE_OK) st = hip_check(launch_rebuild(d, q, false));
+      st = rebuild(s, false, true);
       end_phase(s, ev);
     }
   }
@@ -372,7 +385,7 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
 le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step) {
   if (!s) return LE_E_ARG;
   if (s->host_status) return s->host_status;
-  le_status st = hip_check(launch_rebuild(s->d, s->stream, true));
+  le_status st = rebuild(s, true, false);
   if (st == LE_OK && (x || u)) st = hip_check(launch_state_out(s->d, s->stream, x, u, nullptr, nullptr));
   if (st == LE_OK && f) {
     // the total force lives with the velocities; reuse the state scatter on it
@@ -398,9 +411,11 @@ le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors) {
   if (!s) return LE_E_ARG;
   le_status st = read_status(s);
   Ctrl c;
+  Flags f;
   if (hipMemcpy(&c, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return LE_E_HIP;
+  if (hipMemcpy(&f, s->d.flags, sizeof(Flags), hipMemcpyDeviceToHost) != hipSuccess) return LE_E_HIP;
   if (rebuilds) *rebuilds = c.n_rebuilds;
-  if (max_neighbors) *max_neighbors = c.max_nb;
+  if (max_neighbors) *max_neighbors = f.max_nb;
   return st;
 }
 

@@ -12,15 +12,19 @@ namespace le {
 constexpr int kBlock = 256;        // threads per block of the streaming per-particle kernels
 constexpr int kTile = 128;         // particles (= threads) per tile of the pair kernels
 constexpr int kHalo = 2048;        // positions a tile stages in LDS (slot kHalo: far sentinel)
+static_assert(kHalo % (4 * kTile) == 0, "halo staging loops assume whole rounds of the tile");
 constexpr int kMaxRows = 3;        // cell rows a tile may span and still be staged
 constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile
 constexpr int kPlainBatch = 8;     // padding of the plain list (LDS gathers in flight)
 constexpr int kOtherBatch = 4;     // padding of the imaged / global lists
-constexpr int kScanChunk = 2048;   // cells per block of the cell-count scan
+constexpr int kScanBlock = 1024;   // threads of the single-block cell-count scan
 constexpr int kStressComps = 12;   // 6 kinetic + 6 virial partial sums per block
 
 // Mutable per-simulation scalars that live on the device so that a step
-// never needs the host: step counter, offset, rebuild bookkeeping, status.
+// never needs the host: step counter, offset, rebuild bookkeeping.  Two
+// copies alternate: the kernel that advances the step reads one and writes
+// the other (every block reads, one block writes), so no block ever sees a
+// half-updated state; the host passes the current copy to each launch.
 struct alignas(64) Ctrl {
   int64_t step;          // index n of the current state
   int64_t rebuild_step;  // step of the last neighbour-list build (m)
@@ -28,15 +32,17 @@ struct alignas(64) Ctrl {
   double Delta;          // offset of step n, in [0, L_x)
   double Delta_ref;      // offset at the last build
   double drift;          // sum over steps since the build of dt * max |peculiar velocity|
-  unsigned long long vmax_bits;  // running max of |c| in the current step (bits of a double >= 0)
+  unsigned long long vmax_bits;  // running max of |c|^2 of the last drift (bits of a double >= 0)
   int32_t pos_cur;       // which position buffer holds the current positions
   int32_t aux_cur;       // which velocity/force/tag buffer is current
-  int32_t rebuild;       // 1: rebuild before the next force evaluation
-  int32_t status;        // sticky device status (LE_OK or an LE_E_* code)
+  int32_t rebuild;       // 1: the lists are (being) rebuilt for this state
   int32_t wraps;         // whole L_x folds of the offset since the build
+};
+
+// Sticky status and telemetry shared by both control copies.
+struct alignas(64) Flags {
+  int32_t status;        // LE_OK or the first LE_E_* code latched by a kernel
   int32_t max_nb;        // largest neighbour count of the last build
-  uint32_t spare;
-  int32_t pad;
 };
 
 // Everything a kernel needs, passed by value.
@@ -74,10 +80,10 @@ struct Dev {
   int32_t* slot_of_tag;            // tag -> slot
   int32_t* cell_of;                // cell of each slot (binning pass)
   int32_t* rank;                   // arrival rank inside the cell (binning pass)
-  int32_t* src;                    // scatter target -> source slot
+  int32_t bcap;                    // bucket capacity per cell
+  int32_t* bucket;                 // [ncell][bcap] slots binned into each cell (arrival order)
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
-  int32_t* block_sums;             // [ceil(ncell / kScanChunk)]
   // Neighbour lists.  Entry k of particle i lives in a block of consecutive
   // entries of that particle: blocks of 8 (one 16-byte load) for nl16, of 4
   // for nlo/nlc; block b of particles i, i+1, ... is contiguous.
@@ -97,7 +103,8 @@ struct Dev {
   int32_t ntiles;
   int32_t* bond;                   // [2][np] slot of the chain neighbour below/above, -1 if none
   double* partials;                // [nblocks][kStressComps] (nblocks = ntiles)
-  Ctrl* ctrl;
+  Ctrl* ctrl;                      // current control copy (see Ctrl)
+  Flags* flags;
 };
 
 // Image code of an imaged neighbour: sx in [-3, 3], sy and sz in [-1, 1].
@@ -114,9 +121,11 @@ __host__ __device__ inline void unpack_img(uint8_t c, int& sx, int& sy, int& sz)
 // hipError_t of the launch.
 enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 };
 
-hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force);
+// launch_rebuild reads control copy d.ctrl and writes `next`, which the
+// following launches must then be given.  control: advance the step first
+// (after a drift); force: rebuild whatever the criterion says.
+hipError_t launch_rebuild(const Dev& d, Ctrl* next, hipStream_t s, bool force, bool control);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
-hipError_t launch_control(const Dev& d, hipStream_t s);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
                         double* sample_out);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);

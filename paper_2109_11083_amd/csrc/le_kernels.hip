@@ -30,7 +30,7 @@ __device__ __forceinline__ int xcd_block(int nblocks) {
   return x * q + (x < r ? x : r) + k;
 }
 
-__device__ __forceinline__ void latch(Ctrl* c, int32_t st) { atomicCAS(&c->status, 0, st); }
+__device__ __forceinline__ void latch(Flags* f, int32_t st) { atomicCAS(&f->status, 0, st); }
 
 // Canonical periodic wrap into [0, L); returns the net number of box lengths
 // subtracted (the Lees-Edwards crossing count for the gradient axis).
@@ -114,149 +114,197 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     c->vmax_bits = 0ull;
     c->pos_cur = 0;
     c->aux_cur = 0;
-    c->rebuild = 1;
-    c->status = 0;
+    c->rebuild = 0;
     c->wraps = 0;
-    c->max_nb = 0;
-    c->spare = 0u;
+    d.flags->status = 0;
+    d.flags->max_nb = 0;
   }
 }
 
 // ------------------------------------------------------------- rebuild
-// Rebuild kernels run when the device flag asks for it (or `force`), and are
-// otherwise empty launches.  Order: wrap+bin, scan (2 kernels), scatter,
-// rank+permute, neighbour lists, finish.
-__device__ __forceinline__ bool rebuild_off(const Dev& d, int force) {
-  const Ctrl* c = d.ctrl;
-  return c->status != 0 || !(force || c->rebuild);
+// Four kernels, each an empty launch unless the lists are rebuilt for the
+// current state: (1) advance the step and decide, then crossing + wrap + bin,
+// (2) cell-count scan, (3) rank by tag + permute, (4) neighbour lists.
+
+// Advance the step counter and the offset, adopt the drifted positions, and
+// decide whether the neighbour lists must be rebuilt before the next force
+// evaluation.  Pair displacements evolve as d' = d + dt (c_i - c_j) +
+// gamma_dot dt d_y e_x, so after a strain s = |gamma_dot| (t - t_build) and a
+// peculiar path bound D = sum dt max|c|, a pair within rc now was within
+// g (rc + 2 g D) at the build, g = s/2 + sqrt(1 + s^2/4) the norm of the
+// inverse shear.  The lists (radius rc + skin) stay complete while that bound
+// is below rc + skin.  Pure: every block evaluates it on its own copy.
+__device__ __forceinline__ void control_advance(const Dev& d, Ctrl& c) {
+  double vmax = sqrt(__longlong_as_double((long long)c.vmax_bits));
+  c.vmax_bits = 0ull;
+  c.drift += d.dt * vmax;
+  c.step += 1;
+  c.Delta = le_offset(c.step, d.dt, d.sv, d.Lx);
+  c.pos_cur ^= 1;
+  double T = (double)(c.step - c.rebuild_step) * d.dt;
+  c.wraps = (int)rint((c.Delta_ref + d.sv * T - c.Delta) / d.Lx);
+  double s = fabs(d.shear_rate) * T;
+  double g = 0.5 * s + sqrt(1.0 + 0.25 * s * s);
+  double rc = sqrt(d.rc2);
+  double need = g * (rc + 2.0 * g * c.drift);
+  c.rebuild = (d.rlist <= rc || need >= d.rlist * (1.0 - 1e-9)) ? 1 : 0;
 }
 
-// Boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
-// x and z, then the cell of every particle and its arrival rank in the cell.
-__global__ void k_wrap_bin(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
-  Ctrl* c = d.ctrl;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) c->max_nb = 0;
-  if (i >= d.n) return;
+// The bookkeeping of a rebuild, applied to the state the rebuild produces:
+// sorted copies go to the other buffers, the offset and step become the
+// reference of the co-moving criterion.
+__device__ __forceinline__ void rebuild_adopt(Ctrl& c) {
+  c.pos_cur ^= 1;
+  c.aux_cur ^= 1;
+  c.rebuild = 1;
+  c.rebuild_step = c.step;
+  c.Delta_ref = c.Delta;
+  c.drift = 0.0;
+  c.wraps = 0;
+  c.n_rebuilds += 1;
+}
+
+__device__ __forceinline__ bool rebuild_off(const Dev& d) {
+  return d.flags->status != 0 || !d.ctrl->rebuild;
+}
+
+// (1) Reads control copy d.ctrl and writes the next one (block 0).  With
+// `control` the step is advanced first (after a drift).  On a rebuild:
+// boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
+// x and z in place, then each particle's cell and its arrival rank there.
+// Runs of equal cells within a wave take one atomic per run.
+__global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict__ next, int force,
+                                                        int control) {
+  __shared__ Ctrl sc;
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    Ctrl c = *d.ctrl;
+    const bool ok = d.flags->status == 0;
+    if (ok && control) control_advance(d, c);
+    const bool rb = ok && (force || c.rebuild);
+    sc = c;  // buffers and offset of the state being binned
+    go = rb ? 1 : 0;
+    if (blockIdx.x == 0) {
+      Ctrl o = c;
+      o.rebuild = 0;
+      if (rb) {
+        rebuild_adopt(o);
+        d.flags->max_nb = 0;
+      }
+      *next = o;
+    }
+  }
+  __syncthreads();
+  if (!go) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int np = d.np;
-  double4* P = reinterpret_cast<double4*>(d.pos[c->pos_cur]);
-  double* U = d.vel[c->aux_cur];
-  double4 p = P[i];
-  double x = p.x, y = p.y, z = p.z;
-  double ux = U[i];
-  const double Delta = c->Delta;
-  double ky = wrap1(y, d.Ly);
-  x = x - ky * Delta;
-  ux = ux - ky * d.sv;
-  wrap1(x, d.Lx);
-  wrap1(z, d.Lz);
-  double uy = U[np + i], uz = U[2 * np + i];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
-    latch(c, LE_E_NONFINITE);
-    x = 0.0; y = 0.0; z = 0.0;
+  int cell = -1;
+  if (i < d.n) {
+    double4* P = reinterpret_cast<double4*>(d.pos[sc.pos_cur]);
+    double* U = d.vel[sc.aux_cur];
+    double4 p = P[i];
+    double x = p.x, y = p.y, z = p.z;
+    double ux = U[i];
+    const double Delta = sc.Delta;
+    double ky = wrap1(y, d.Ly);
+    x = x - ky * Delta;
+    ux = ux - ky * d.sv;
+    wrap1(x, d.Lx);
+    wrap1(z, d.Lz);
+    double uy = U[np + i], uz = U[2 * np + i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
+      latch(d.flags, LE_E_NONFINITE);
+      x = 0.0; y = 0.0; z = 0.0;
+    }
+    p.x = x; p.y = y; p.z = z;
+    P[i] = p;
+    U[i] = ux;
+    int ix = cell_index(x, d.inv_lx, d.nx);
+    int iy = cell_index(y, d.inv_ly, d.ny);
+    int iz = cell_index(z, d.inv_lz, d.nz);
+    cell = (iz * d.ny + iy) * d.nx + ix;
+    d.cell_of[i] = cell;
   }
-  p.x = x; p.y = y; p.z = z;
-  P[i] = p;
-  U[i] = ux;
-  int ix = cell_index(x, d.inv_lx, d.nx);
-  int iy = cell_index(y, d.inv_ly, d.ny);
-  int iz = cell_index(z, d.inv_lz, d.nz);
-  int cell = (iz * d.ny + iy) * d.nx + ix;
-  d.cell_of[i] = cell;
-  d.rank[i] = atomicAdd(&d.cell_count[cell], 1);
+  // runs of equal cells among consecutive lanes share one atomic
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(cell, 1, 64);
+  const bool head = lane == 0 || prev != cell;
+  const unsigned long long heads = __ballot(head);
+  const int run0 = 63 - __clzll(heads & ((2ull << lane) - 1ull));  // lane 63: mask all ones
+  const unsigned long long after = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1ull));
+  const int run1 = after ? __ffsll((long long)after) - 1 : 64;  // first lane of the next run
+  int base = 0;
+  if (head && cell >= 0) base = atomicAdd(&d.cell_count[cell], run1 - lane);
+  base = __shfl(base, run0, 64);
+  if (cell >= 0) {
+    const int r = base + (lane - run0);
+    d.rank[i] = r;
+    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = i;
+    else latch(d.flags, LE_E_CAPACITY);
+  }
 }
 
-// Exclusive scan of the cell counts, pass 1: per-chunk scan + chunk totals.
-__global__ void k_scan_local(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
-  __shared__ int wsum[kBlock / 64];
-  const int per = kScanChunk / kBlock;  // cells per thread
-  int base = blockIdx.x * kScanChunk + threadIdx.x * per;
-  int v[per];
-  int s = 0;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    int c = base + q;
-    v[q] = (c < d.ncell) ? d.cell_count[c] : 0;
-    s += v[q];
-  }
-  // inclusive scan of thread sums across the block
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int incl = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += t;
-  }
-  if (lane == 63) wsum[wid] = incl;
+// (2) Exclusive scan of the cell counts into cell_start (one block); the
+// counts are cleared for the next binning pass.
+__global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) {
+  if (rebuild_off(d)) return;
+  __shared__ int wsum[kScanBlock / 64];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
-  int woff = 0;
-  for (int w = 0; w < wid; ++w) woff += wsum[w];
-  int excl = woff + incl - s;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    int c = base + q;
-    if (c < d.ncell) d.cell_start[c] = excl;
-    excl += v[q];
-  }
-  if (threadIdx.x == kBlock - 1) d.block_sums[blockIdx.x] = woff + incl;
-}
-
-// Pass 2: add the total of all earlier chunks to each chunk.
-__global__ void k_scan_add(Dev d, int force, int nchunks) {
-  if (rebuild_off(d, force)) return;
-  __shared__ int red[kBlock];
-  int t = 0;
-  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) t += d.block_sums[b];
-  red[threadIdx.x] = t;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < d.ncell; c0 += kScanBlock) {
+    const int c = c0 + threadIdx.x;
+    const int v = c < d.ncell ? d.cell_count[c] : 0;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+      if (w < wid) woff += wsum[w];
+      tot += wsum[w];
+    }
+    if (c < d.ncell) {
+      d.cell_start[c] = carry + woff + incl - v;
+      d.cell_count[c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
     __syncthreads();
   }
-  int off = red[0];
-  int base = blockIdx.x * kScanChunk;
-  for (int q = threadIdx.x; q < kScanChunk; q += kBlock) {
-    int c = base + q;
-    if (c < d.ncell) d.cell_start[c] += off;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
-  (void)nchunks;
+  if (threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
 }
 
-__global__ void k_scatter(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  d.src[d.cell_start[d.cell_of[i]] + d.rank[i]] = i;
-}
-
-// Deterministic in-cell order: the final slot of a particle is the cell start
-// plus the number of cell-mates with a smaller tag.  Gathers every field
-// into the other buffer set.
-__global__ void k_rank_permute(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
+// (3) Final slot = cell start + number of cell-mates with a smaller tag, so
+// the order is (cell, tag) whatever the arrival order; copy the particle's
+// state to the other buffers at that slot.
+__global__ void __launch_bounds__(kBlock) k_permute(Dev d) {
+  if (rebuild_off(d)) return;
   const Ctrl* c = d.ctrl;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
   const int np = d.np;
-  const int pc = c->pos_cur, ac = c->aux_cur;
-  const int32_t* tag = d.tag[ac];
-  int i = d.src[p];
-  int cell = d.cell_of[i];
-  int s0 = d.cell_start[cell], s1 = d.cell_start[cell + 1];
-  int t = tag[i];
+  const int pd = c->pos_cur, ad = c->aux_cur;  // destination buffers
+  const int ps = 1 - pd, as = 1 - ad;          // binned (source) buffers
+  const int32_t* tag = d.tag[as];
+  const int cell = d.cell_of[i];
+  const int s0 = d.cell_start[cell], cnt = min(d.cell_start[cell + 1] - s0, d.bcap);
+  const int t = tag[i];
+  const int32_t* B = d.bucket + (size_t)cell * d.bcap;
   int r = 0;
-  for (int q = s0; q < s1; ++q) r += (tag[d.src[q]] < t) ? 1 : 0;
-  int ns = s0 + r;
-  reinterpret_cast<double4*>(d.pos[1 - pc])[ns] = reinterpret_cast<const double4*>(d.pos[pc])[i];
+  for (int q = 0; q < cnt; ++q) r += (tag[B[q]] < t) ? 1 : 0;
+  const int ns = s0 + r;
+  reinterpret_cast<double4*>(d.pos[pd])[ns] = reinterpret_cast<const double4*>(d.pos[ps])[i];
   for (int a = 0; a < 3; ++a) {
-    d.vel[1 - ac][a * np + ns] = d.vel[ac][a * np + i];
-    d.frc[1 - ac][a * np + ns] = d.frc[ac][a * np + i];
+    d.vel[ad][a * np + ns] = d.vel[as][a * np + i];
+    d.frc[ad][a * np + ns] = d.frc[as][a * np + i];
   }
-  d.tag[1 - ac][ns] = t;
+  d.tag[ad][ns] = t;
   d.slot_of_tag[t] = ns;
-  d.cell_count[cell] = 0;  // ready for the next binning pass
 }
 
 // Neighbour lists of radius r_list through the Lees-Edwards cell stencil.
@@ -343,7 +391,7 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
   return r2 < d.rlist2;
 }
 
-__global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
+__global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[kHalo + 8], hy[kHalo + 8], hz[kHalo + 8];
@@ -353,7 +401,7 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
   __shared__ uint16_t lspare[kTile];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
-  if (threadIdx.x == 0) skip = rebuild_off(d, force) ? 1 : 0;
+  if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const int np = d.np, K = d.K, n = d.n;
@@ -361,7 +409,7 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
   const int s0 = tile * kTile;
   const int i = s0 + threadIdx.x;
   const bool valid = i < n;
-  const int pn = 1 - c->pos_cur, an = 1 - c->aux_cur;
+  const int pn = c->pos_cur, an = c->aux_cur;  // sorted buffers of the new state
   const double4* P = reinterpret_cast<const double4*>(d.pos[pn]);
   const double Delta = c->Delta;
   const double rmarg = d.rlist * (1.0 + 1e-12) + 1e-12 * (d.Lx + d.Ly + d.Lz);
@@ -627,13 +675,13 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
   {  // telemetry: one atomic per wave
     int mx = npl + nog;
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(&c->max_nb, mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(&d.flags->max_nb, mx);
   }
   if (!valid) return;
   int npl_p = (npl + kPlainBatch - 1) / kPlainBatch * kPlainBatch;
   int nog_p = (nog + kOtherBatch - 1) / kOtherBatch * kOtherBatch;
   if (npl_p > K || nog_p > K) {
-    latch(c, LE_E_CAPACITY);
+    latch(d.flags, LE_E_CAPACITY);
     npl_p = nog_p = 0;
   } else {
     if (npl < npl_p) {  // pad and flush the partial block
@@ -660,48 +708,10 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d, int force) {
   }
 }
 
-__global__ void k_rebuild_finish(Dev d, int force) {
-  if (rebuild_off(d, force)) return;
-  Ctrl* c = d.ctrl;
-  c->pos_cur ^= 1;
-  c->aux_cur ^= 1;
-  c->rebuild = 0;
-  c->rebuild_step = c->step;
-  c->Delta_ref = c->Delta;
-  c->drift = 0.0;
-  c->wraps = 0;
-  c->n_rebuilds += 1;
-}
-
 // ---------------------------------------------------------- integrator
 __device__ __forceinline__ void vmax_commit(Ctrl* c, double v2) {
   double m = wave_max(v2);
   if ((threadIdx.x & 63) == 0) atomicMax(&c->vmax_bits, (unsigned long long)__double_as_longlong(m));
-}
-
-// Advance the step counter and the offset, adopt the new positions, and
-// decide whether the neighbour lists must be rebuilt before the next force
-// evaluation.  Pair displacements evolve as d' = d + dt (c_i - c_j) +
-// gamma_dot dt d_y e_x, so after a strain s = |gamma_dot| (t - t_build) and a
-// peculiar path bound D = sum dt max|c|, a pair within rc now was within
-// g (rc + 2 g D) at the build, g = s/2 + sqrt(1 + s^2/4) the norm of the
-// inverse shear.  The lists (radius rc + skin) stay complete while that bound
-// is below rc + skin.  Runs on one thread after every block of the drift
-// kernel has finished.
-__device__ void control_update(const Dev& d, Ctrl* c) {
-  double vmax = sqrt(__longlong_as_double((long long)c->vmax_bits));
-  c->vmax_bits = 0ull;
-  c->drift += d.dt * vmax;
-  c->step += 1;
-  c->Delta = le_offset(c->step, d.dt, d.sv, d.Lx);
-  c->pos_cur ^= 1;
-  double T = (double)(c->step - c->rebuild_step) * d.dt;
-  c->wraps = (int)rint((c->Delta_ref + d.sv * T - c->Delta) / d.Lx);
-  double s = fabs(d.shear_rate) * T;
-  double g = 0.5 * s + sqrt(1.0 + 0.25 * s * s);
-  double rc = sqrt(d.rc2);
-  double need = g * (rc + 2.0 * g * c->drift);
-  if (d.rlist <= rc || need >= d.rlist * (1.0 - 1e-9)) c->rebuild = 1;
 }
 
 // Sum the per-block stress partials (fixed order) and write the stress
@@ -735,12 +745,12 @@ __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
 }
 
 // First half-kick and drift from a state with full-step velocities:
-// u += dt/(2m) F ; x_new = x + dt u (into the other position buffer); the
-// last block then advances the step (control_update).
+// u += dt/(2m) F ; x_new = x + dt u (into the other position buffer).  The
+// step is advanced by the next control kernel.
 __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
   __shared__ int skip;
   Ctrl* c = d.ctrl;
-  if (threadIdx.x == 0) skip = c->status;
+  if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -763,16 +773,9 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     q.z = p.z + d.dt * uz;
     q.w = p.w;
     reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
-    if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(c, LE_E_NONFINITE);
+    if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
   }
   vmax_commit(c, v2);
-}
-
-// One thread: advance the step after a drift (see control_update).
-__global__ void k_control(Dev d) {
-  Ctrl* c = d.ctrl;
-  if (c->status) return;
-  control_update(d, c);
 }
 
 // ---------------------------------------------------------- force kernel
@@ -848,7 +851,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
   __shared__ double hx[kHalo + 1], hy[kHalo + 1], hz[kHalo + 1];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
-  if (threadIdx.x == 0) skip = c->status;
+  if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
   const int lb = xcd_block(d.ntiles);
@@ -977,7 +980,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
         if (!(r2 < d.fene_r02)) {
-          latch(c, LE_E_BOND);
+          latch(d.flags, LE_E_BOND);
           continue;
         }
         double f = -d.fene_k / (1.0 - r2 / d.fene_r02);
@@ -1034,7 +1037,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
         q.z = pi.z + d.dt * uz;
         q.w = pi.w;
         reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
-        if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(c, LE_E_NONFINITE);
+        if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
       }
       U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
     }
@@ -1051,7 +1054,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
 // Stand-alone reduction of the block partials (le_forces, le_stress).
 __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
   __shared__ int skip;
-  if (threadIdx.x == 0) skip = d.ctrl->status;
+  if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
   reduce_partials(d, out6, virial_only != 0);
@@ -1059,7 +1062,7 @@ __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
 
 // ----------------------------------------------------------- state out
 __global__ void k_state_out(Dev d, double* x, double* u, int32_t* cell_of, int32_t* order) {
-  if (d.ctrl->status) return;
+  if (d.flags->status) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const Ctrl* c = d.ctrl;
@@ -1079,7 +1082,7 @@ __global__ void k_state_out(Dev d, double* x, double* u, int32_t* cell_of, int32
 }
 
 __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long long* counter) {
-  if (d.ctrl->status) return;
+  if (d.flags->status) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const int np = d.np;
@@ -1129,25 +1132,17 @@ hipError_t launch_load_state(const Dev& d, hipStream_t s, const double* x0, cons
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild(const Dev& d, hipStream_t s, bool force) {
-  int f = force ? 1 : 0;
-  int nb = blocks_for(d.n);
-  int nchunks = (d.ncell + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_wrap_bin, dim3(nb), dim3(kBlock), 0, s, d, f);
-  hipLaunchKernelGGL(k_scan_local, dim3(nchunks), dim3(kBlock), 0, s, d, f);
-  hipLaunchKernelGGL(k_scan_add, dim3(nchunks), dim3(kBlock), 0, s, d, f, nchunks);
-  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, s, d, f);
-  hipLaunchKernelGGL(k_rank_permute, dim3(nb), dim3(kBlock), 0, s, d, f);
-  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(kTile), 0, s, d, f);
-  hipLaunchKernelGGL(k_rebuild_finish, dim3(1), dim3(1), 0, s, d, f);
+hipError_t launch_rebuild(const Dev& d, Ctrl* next, hipStream_t s, bool force, bool control) {
+  // kernels after the first see the control copy it writes
+  Dev dn = d;
+  dn.ctrl = next;
+  hipLaunchKernelGGL(k_control_bin, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, next, force ? 1 : 0,
+                     control ? 1 : 0);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, dn);
+  hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
+  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(kTile), 0, s, dn);
   return hipGetLastError();
 }
-
-hipError_t launch_control(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, d);
-  return hipGetLastError();
-}
-
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d);
   return hipGetLastError();
