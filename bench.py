@@ -32,6 +32,7 @@ PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 vector (also the unpacked FP32 vecto
 PEAK_HBM_GBS = 8000.0
 PAIR_FLOPS = 26.0             # per in-cutoff pair, counted once per unordered pair
 STEP_FLOPS = 40.0             # thermostat + velocity Verlet per particle
+BYTES_FUSED = 100.0           # fused step, per particle: read x, u, tag; write x, u
 
 
 def log(msg):
@@ -47,11 +48,30 @@ def lj_params(n, shear_rate, precision, seed=21, skin=0.3):
     return w, p
 
 
-def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True, skin=0.3):
+KG_CHAINS, KG_LEN = 2000, 200
+
+
+def kg_params(shear_rate, precision, seed=31, skin=0.3, n_chains=KG_CHAINS, chain_len=KG_LEN):
+    """Kremer-Grest melt: WCA + FENE(30, 1.5), density 0.85, T=1, gamma=0.5, dt=0.01,
+    overlap-free lattice-path start (stands in for the warmed-up random-walk melt)."""
+    from paper_2109_11083_amd import inputs
+    from paper_2109_11083_amd.sim import Params
+    w = inputs.kg_workload(n_chains, chain_len, shear_rate=shear_rate, seed=seed, layout="snake")
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, skin=skin,
+               precision=precision, rc=2.0 ** (1.0 / 6.0), pair="wca", n_chains=n_chains,
+               chain_len=chain_len, dt=0.01, kT=1.0, gamma=0.5)
+    return w, p
+
+
+def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True, skin=0.3,
+            workload="lj"):
     import torch
     from paper_2109_11083_amd import binding as B
     from paper_2109_11083_amd.sim import Sim
-    w, p = lj_params(n, shear_rate, precision, skin=skin)
+    if workload == "kg":
+        w, p = kg_params(shear_rate, precision, skin=skin)
+    else:
+        w, p = lj_params(n, shear_rate, precision, skin=skin)
     sim = Sim(p, w.x, w.u, step0=0)
     ring = torch.zeros((max(steps // sample_every, 1), 6), dtype=torch.float64, device="cuda")
     if warmup > 0:
@@ -75,10 +95,12 @@ def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=Tru
     if len(tail) >= 20:
         blocks = tail[: len(tail) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / shear_rate
         eta_se = float(blocks.std(ddof=1) / math.sqrt(10))
+    prof = sim.observables(50)
     out = dict(n=p.n, seconds=t1 - t0, steps=steps, value=p.n * steps / (t1 - t0),
                ms_per_step=1e3 * (t1 - t0) / steps, phases=phases,
                rebuilds=st1["rebuilds"] - st0["rebuilds"], max_neighbors=st1["max_neighbors"],
-               eta=eta, eta_se=eta_se, box=p.box, rc=p.rc)
+               eta=eta, eta_se=eta_se, box=p.box, rc=p.rc,
+               ux_profile=[float(v) for v in prof["sum_ux"] / prof["count"]], kT=prof["kT"])
     sim.close()
     return out
 
@@ -126,6 +148,8 @@ def main():
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events in the timed region (then no per-kernel roofline)")
     ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--workload", default="lj", choices=["lj", "kg"],
+                    help="lj: 256,000-particle LJ fluid (the headline); kg: 2000 x 200 Kremer-Grest melt")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -139,10 +163,10 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    log(f"bench: LJ n={args.n} shear_rate={args.shear_rate} {args.precision} "
+    log(f"bench: {args.workload} n={args.n} shear_rate={args.shear_rate} {args.precision} "
         f"steps={args.steps} warmup={args.warmup}")
     r = run_gpu(args.n, args.shear_rate, args.precision, args.steps, args.warmup,
-                timing=not args.no_timing, skin=args.skin)
+                timing=not args.no_timing, skin=args.skin, workload=args.workload)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, phases={r['phases']}")
 
@@ -164,15 +188,26 @@ def main():
     if not args.no_extra:
         for sr in (0.01, 1.0):
             e = run_gpu(args.n, sr, args.precision, 2000, 100, skin=args.skin)
-            extra[f"shear_rate_{sr}"] = dict(value=e["value"], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
-                                             eta=e["eta"])
+            extra[f"lj_shear_rate_{sr}"] = dict(value=e["value"], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
+                                                eta=e["eta"])
             log(f"bench: shear_rate={sr}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
+        # mixed vs FP64 on the same workload: throughput and viscosity with its error bar
         other = "mixed" if args.precision == "fp64" else "fp64"
-        m = run_gpu(args.n, args.shear_rate, other, 2000, 100, skin=args.skin)
-        extra[f"{other}_value"] = m["value"]
+        m = run_gpu(args.n, args.shear_rate, other, args.steps, args.warmup, skin=args.skin)
         fm, fn = m["phases"]["force"]
-        extra[f"{other}_force_kernel_us"] = 1e3 * fm / max(fn, 1)
-        log(f"bench: {other}: {m['value']:.4e} p-steps/s")
+        extra[f"lj_{other}"] = dict(value=m["value"], force_kernel_us=1e3 * fm / max(fn, 1),
+                                    eta=m["eta"], eta_se=m["eta_se"],
+                                    eta_diff_vs_main=(m["eta"] - r["eta"]) if r["eta"] is not None else None)
+        log(f"bench: {other}: {m['value']:.4e} p-steps/s eta={m['eta']}")
+        # Kremer-Grest melt, 2000 chains x 200 beads (HBM-bound pair kernel)
+        k = run_gpu(0, 0.01, args.precision, 2000, 100, skin=args.skin, workload="kg")
+        kf, kn = k["phases"]["force"]
+        kus = 1e3 * kf / max(kn, 1)
+        extra["kg_2000x200"] = dict(value=k["value"], force_kernel_us=kus,
+                                    force_kernel_GBs_algorithmic=k["n"] * BYTES_FUSED / (kus * 1e-6) / 1e9,
+                                    rebuilds_per_1000=1000 * k["rebuilds"] / 2000, eta=k["eta"],
+                                    shear_rate=0.01)
+        log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -207,6 +242,8 @@ def main():
         "rebuilds_per_1000_steps": round(1000.0 * r["rebuilds"] / args.steps, 2),
         "phase_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()},
         "viscosity": {"eta": r["eta"], "block_se": r["eta_se"], "window": "last 20% of the timed steps"},
+        "ux_profile_50_bins": [round(v, 5) for v in r["ux_profile"]],
+        "kT_kinetic": r["kT"],
         "extra": extra,
     }
     print(json.dumps(out), flush=True)

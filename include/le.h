@@ -100,7 +100,9 @@ typedef struct le_params {
   int32_t precision;   /* LE_FP64 or LE_MIXED                                       */
   int32_t cells[3];    /* cell grid; 0 = floor(L_a / (rc + skin)); each must be >= 3 */
   int32_t max_neighbors; /* neighbour-list capacity per particle; 0 = from density  */
-  int32_t tune;        /* launch-shape selector (0 = default); results do not depend on it */
+  int32_t tune;        /* pair-kernel layout: 0 = chosen from density, 1 = partners staged
+                          in an LDS halo per tile, 2 = partners read from global memory;
+                          the physics is the same (sums may differ in the last bits) */
 } le_params;
 
 /* Device bytes needed for a simulation with these parameters.  Pure host
@@ -152,6 +154,17 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
  * conservative forces only; order xx, yy, zz, xy, xz, yz.  The viscosity of
  * Eq. viscosity is <sigma_xy> / shear_rate.  sigma6: device float64[6]. */
 le_status le_stress(le_sim* s, double* sigma6);
+
+/* Observables of the current state (Fig. profile; Section 3): the particle
+ * count and the summed lab flow velocity u_x in nbins equal bins along the
+ * gradient axis y (each particle counted at its image inside the box, with
+ * the velocity of that image), the kinetic temperature sum_i m c_i^2 / (3n-3)
+ * of the peculiar velocities (Eq. vi), and the centre-of-mass lab velocity.
+ * out: device float64[2*nbins + 4] = count[nbins], sum_ux[nbins], kT, com[3].
+ * 1 <= nbins <= LE_MAX_BINS.  Sums are taken in a fixed order (reproducible).
+ * Does not change the state. */
+#define LE_MAX_BINS 256
+le_status le_observables(le_sim* s, int32_t nbins, double* out);
 
 /* Copy the current state out in tag order: positions x, lab velocities u and
  * the total force f of the current step (device float64 [3][n] each; any may

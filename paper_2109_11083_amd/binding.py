@@ -30,8 +30,9 @@ LE_MIXED = 1
 EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
-    "le_timing_enable", "le_timing_read",
+    "le_timing_enable", "le_timing_read", "le_observables",
 ]
+LE_MAX_BINS = 256
 
 
 class le_params(C.Structure):
@@ -97,6 +98,7 @@ def lib() -> C.CDLL:
     L.le_philox.argtypes = [vp, vp, vp, i64, vp]
     L.le_timing_enable.argtypes = [vp, i32]
     L.le_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+    L.le_observables.argtypes = [vp, i32, vp]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -179,6 +181,10 @@ def le_offsets(shear_rate: float, Lx: float, Ly: float, dt: float, step0: int, c
 
 def le_philox(ctr: int, key: int, out: int, count: int, stream: int | None) -> None:
     check(lib().le_philox(ctr, key, out, count, stream), "le_philox")
+
+
+def le_observables(sim: int, nbins: int, out: int) -> None:
+    check(lib().le_observables(sim, nbins, out), "le_observables")
 
 
 def le_timing_enable(sim: int, enabled: bool) -> None:

@@ -17,6 +17,7 @@ struct le_sim {
   hipStream_t stream;
   int32_t host_status;                 // last status seen by a synchronising call
   Ctrl* ctrl_base;                     // the two control copies; d.ctrl is the current one
+  unsigned long long* vmax_base;       // the two speed-bound slot arrays (d.vmax current)
   unsigned long long* counter;         // device scratch counter (pairs_out)
   double* scratch6;                    // device 6 doubles
   // phase timing (le_timing_enable)
@@ -53,6 +54,7 @@ le_status validate(const le_params* p, Geometry* g) {
     return LE_E_ARG;
   if (p->pair != LE_PAIR_LJ && p->pair != LE_PAIR_WCA) return LE_E_ARG;
   if (p->precision != LE_FP64 && p->precision != LE_MIXED) return LE_E_ARG;
+  if (p->tune < 0 || p->tune > 2) return LE_E_ARG;
   double rc = p->rc;
   if (rc <= 0.0) rc = (p->pair == LE_PAIR_WCA) ? pow(2.0, 1.0 / 6.0) * p->sigma : 2.5 * p->sigma;
   if (p->chain_len < 0 || p->n_chains < 0) return LE_E_ARG;
@@ -106,6 +108,8 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   memset(&t, 0, sizeof(t));
   t.ctrl = (Ctrl*)take(2 * sizeof(Ctrl));
   t.flags = (Flags*)take(sizeof(Flags));
+  t.vmax = (unsigned long long*)take(2 * kSlots * kLineU64 * sizeof(unsigned long long));
+  t.scan_status = (unsigned long long*)take(((ncell + kScanTile - 1) / kScanTile) * sizeof(unsigned long long));
   for (int b = 0; b < 2; ++b) {
     t.pos[b] = (double*)take(4 * np * sizeof(double));
     t.vel[b] = (double*)take(3 * np * sizeof(double));
@@ -128,12 +132,16 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.tile_nstage = (int32_t*)take((size_t)g.nblocks * sizeof(int32_t));
   t.bond = (p->chain_len > 0) ? (int32_t*)take(2 * np * sizeof(int32_t)) : nullptr;
   t.partials = (double*)take((size_t)g.nblocks * kStressComps * sizeof(double));
+  t.obs_part = (double*)take((size_t)((p->n + kBlock - 1) / kBlock) * (2 * LE_MAX_BINS + 4) *
+                             sizeof(double));
   unsigned long long* counter = (unsigned long long*)take(sizeof(unsigned long long));
   double* scratch6 = (double*)take(6 * sizeof(double));
   if (d) {
     // copy buffer pointers into d (geometry fields are filled by the caller)
     d->ctrl = t.ctrl;
     d->flags = t.flags;
+    d->vmax = t.vmax;
+    d->scan_status = t.scan_status;
     for (int b = 0; b < 2; ++b) {
       d->pos[b] = t.pos[b]; d->vel[b] = t.vel[b]; d->frc[b] = t.frc[b]; d->tag[b] = t.tag[b];
     }
@@ -144,8 +152,9 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     d->halo_slot = t.halo_slot; d->halo_code = t.halo_code; d->tile_nstage = t.tile_nstage;
     d->bond = t.bond;
     d->partials = t.partials;
+    d->obs_part = t.obs_part;
   }
-  if (s) { s->counter = counter; s->scratch6 = scratch6; s->ctrl_base = t.ctrl; }
+  if (s) { s->counter = counter; s->scratch6 = scratch6; s->ctrl_base = t.ctrl; s->vmax_base = t.vmax; }
   return off + kAlign;  // room to align the caller's base pointer
 }
 
@@ -201,6 +210,17 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->nblocks = g.nblocks;
   d->ntiles = g.nblocks;
   d->bcap = g.bcap;
+  {
+    // LDS halo at force time when partners per particle clearly outnumber the
+    // positions a tile must stage per particle (strip tile of kTile particles:
+    // 9 neighbouring rows of (tile cells + 2) cells)
+    const double rho = (double)p->n / (p->box[0] * p->box[1] * p->box[2]);
+    const double cell_n = rho * (p->box[0] / g.nc[0]) * (p->box[1] / g.nc[1]) * (p->box[2] / g.nc[2]);
+    const double tile_cells = kTile / fmax(cell_n, 1e-9);
+    const double halo_pp = 9.0 * (tile_cells + 2.0) * cell_n / kTile;
+    const double list_pp = 4.0 / 3.0 * M_PI * g.rlist * g.rlist * g.rlist * rho;
+    d->staged = (p->tune == 1) ? 1 : (p->tune == 2) ? 0 : (list_pp >= 3.0 * halo_pp ? 1 : 0);
+  }
 }
 
 le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
@@ -246,9 +266,12 @@ void end_phase(le_sim* s, long k) {
 
 // Rebuild chain; afterwards the other control copy is the current one.
 le_status rebuild(le_sim* s, bool force, bool control) {
-  Ctrl* next = (s->d.ctrl == s->ctrl_base) ? s->ctrl_base + 1 : s->ctrl_base;
-  le_status st = hip_check(launch_rebuild(s->d, next, s->stream, force, control));
+  const bool first = s->d.ctrl == s->ctrl_base;
+  Ctrl* next = first ? s->ctrl_base + 1 : s->ctrl_base;
+  unsigned long long* next_vmax = s->vmax_base + (first ? kSlots * kLineU64 : 0);
+  le_status st = hip_check(launch_rebuild(s->d, next, next_vmax, s->stream, force, control));
   s->d.ctrl = next;
+  s->d.vmax = next_vmax;
   return st;
 }
 
@@ -382,6 +405,12 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   return st;
 }
 
+le_status le_observables(le_sim* s, int32_t nbins, double* out) {
+  if (!s || !out || nbins < 1 || nbins > LE_MAX_BINS) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  return hip_check(launch_observables(s->d, s->stream, nbins, out));
+}
+
 le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step) {
   if (!s) return LE_E_ARG;
   if (s->host_status) return s->host_status;
@@ -415,7 +444,11 @@ le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors) {
   if (hipMemcpy(&c, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return LE_E_HIP;
   if (hipMemcpy(&f, s->d.flags, sizeof(Flags), hipMemcpyDeviceToHost) != hipSuccess) return LE_E_HIP;
   if (rebuilds) *rebuilds = c.n_rebuilds;
-  if (max_neighbors) *max_neighbors = f.max_nb;
+  if (max_neighbors) {
+    int32_t m = 0;
+    for (int k = 0; k < kSlots; ++k) m = f.max_nb_slot[k * kLineInts] > m ? f.max_nb_slot[k * kLineInts] : m;
+    *max_neighbors = m;
+  }
   return st;
 }
 

@@ -17,8 +17,12 @@ constexpr int kMaxRows = 3;        // cell rows a tile may span and still be sta
 constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile
 constexpr int kPlainBatch = 8;     // padding of the plain list (LDS gathers in flight)
 constexpr int kOtherBatch = 4;     // padding of the imaged / global lists
-constexpr int kScanBlock = 1024;   // threads of the single-block cell-count scan
+constexpr int kScanBlock = 1024;   // threads per block of the cell-count scan
 constexpr int kStressComps = 12;   // 6 kinetic + 6 virial partial sums per block
+constexpr int kSlots = 64;         // words (one per 128-byte line) a block maximum is spread over
+constexpr int kLineInts = 32;      // 32-bit words per 128-byte line
+constexpr int kLineU64 = 16;       // 64-bit words per 128-byte line
+constexpr int kScanTile = 8 * kScanBlock;  // cells per block of the cell-count scan
 
 // Mutable per-simulation scalars that live on the device so that a step
 // never needs the host: step counter, offset, rebuild bookkeeping.  Two
@@ -32,7 +36,6 @@ struct alignas(64) Ctrl {
   double Delta;          // offset of step n, in [0, L_x)
   double Delta_ref;      // offset at the last build
   double drift;          // sum over steps since the build of dt * max |peculiar velocity|
-  unsigned long long vmax_bits;  // running max of |c|^2 of the last drift (bits of a double >= 0)
   int32_t pos_cur;       // which position buffer holds the current positions
   int32_t aux_cur;       // which velocity/force/tag buffer is current
   int32_t rebuild;       // 1: the lists are (being) rebuilt for this state
@@ -42,7 +45,9 @@ struct alignas(64) Ctrl {
 // Sticky status and telemetry shared by both control copies.
 struct alignas(64) Flags {
   int32_t status;        // LE_OK or the first LE_E_* code latched by a kernel
-  int32_t max_nb;        // largest neighbour count of the last build
+  // largest neighbour count of the last build: max over kSlots words, one per
+  // 128-byte line (block b updates word b mod kSlots)
+  int32_t max_nb_slot[kSlots * kLineInts];
 };
 
 // Everything a kernel needs, passed by value.
@@ -66,6 +71,7 @@ struct Dev {
   int32_t chain_len;
   int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
   int32_t precision;
+  int32_t staged;                  // 1: partners in the tile's LDS halo; 0: all from global memory
   // FP32 pre-test of the list build: r2 (float, tile-relative coordinates)
   // below nb_lo is certainly inside r_list^2, at or above nb_hi certainly
   // outside; in between the plain FP64 displacement decides.
@@ -103,7 +109,12 @@ struct Dev {
   int32_t ntiles;
   int32_t* bond;                   // [2][np] slot of the chain neighbour below/above, -1 if none
   double* partials;                // [nblocks][kStressComps] (nblocks = ntiles)
+  double* obs_part;                // [ceil(n / kBlock)][2 * LE_MAX_BINS + 4] observable partials
   Ctrl* ctrl;                      // current control copy (see Ctrl)
+  // running max of |c|^2 of the last drift (bits of doubles >= 0) in kSlots
+  // words of kLineU64 stride; two arrays alternate with the control copies
+  unsigned long long* vmax;
+  unsigned long long* scan_status; // [ceil(ncell / kScanTile)] look-back words of the cell scan
   Flags* flags;
 };
 
@@ -124,11 +135,13 @@ enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 
 // launch_rebuild reads control copy d.ctrl and writes `next`, which the
 // following launches must then be given.  control: advance the step first
 // (after a drift); force: rebuild whatever the criterion says.
-hipError_t launch_rebuild(const Dev& d, Ctrl* next, hipStream_t s, bool force, bool control);
+hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vmax, hipStream_t s,
+                          bool force, bool control);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
                         double* sample_out);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
+hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out);
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,
                             int32_t* order);
 hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t cap,

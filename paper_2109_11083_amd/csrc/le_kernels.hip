@@ -111,14 +111,14 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     c->Delta = Delta0;
     c->Delta_ref = Delta0;
     c->drift = 0.0;
-    c->vmax_bits = 0ull;
     c->pos_cur = 0;
     c->aux_cur = 0;
     c->rebuild = 0;
     c->wraps = 0;
     d.flags->status = 0;
-    d.flags->max_nb = 0;
+    for (int k = 0; k < kSlots * kLineInts; ++k) d.flags->max_nb_slot[k] = 0;
   }
+  for (int k = i; k < kSlots * kLineU64; k += gridDim.x * blockDim.x) d.vmax[k] = 0ull;
 }
 
 // ------------------------------------------------------------- rebuild
@@ -134,9 +134,8 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
 // g (rc + 2 g D) at the build, g = s/2 + sqrt(1 + s^2/4) the norm of the
 // inverse shear.  The lists (radius rc + skin) stay complete while that bound
 // is below rc + skin.  Pure: every block evaluates it on its own copy.
-__device__ __forceinline__ void control_advance(const Dev& d, Ctrl& c) {
-  double vmax = sqrt(__longlong_as_double((long long)c.vmax_bits));
-  c.vmax_bits = 0ull;
+__device__ __forceinline__ void control_advance(const Dev& d, Ctrl& c, unsigned long long vbits) {
+  double vmax = sqrt(__longlong_as_double((long long)vbits));
   c.drift += d.dt * vmax;
   c.step += 1;
   c.Delta = le_offset(c.step, d.dt, d.sv, d.Lx);
@@ -173,25 +172,39 @@ __device__ __forceinline__ bool rebuild_off(const Dev& d) {
 // boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
 // x and z in place, then each particle's cell and its arrival rank there.
 // Runs of equal cells within a wave take one atomic per run.
-__global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict__ next, int force,
-                                                        int control) {
+__global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict__ next,
+                                                        unsigned long long* __restrict__ next_vmax,
+                                                        int force, int control) {
   __shared__ Ctrl sc;
   __shared__ int go;
-  if (threadIdx.x == 0) {
-    Ctrl c = *d.ctrl;
+  if (threadIdx.x < 64) {
+    // the drift's speed bound: max over the slot words (first wave)
+    unsigned long long vb = threadIdx.x < kSlots ? d.vmax[threadIdx.x * kLineU64] : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+      unsigned long long t = __shfl_xor(vb, o, 64);
+      vb = t > vb ? t : vb;
+    }
     const bool ok = d.flags->status == 0;
-    if (ok && control) control_advance(d, c);
+    Ctrl c = *d.ctrl;
+    if (ok && control) control_advance(d, c, vb);
     const bool rb = ok && (force || c.rebuild);
-    sc = c;  // buffers and offset of the state being binned
-    go = rb ? 1 : 0;
+    if (threadIdx.x == 0) {
+      sc = c;  // buffers and offset of the state being binned
+      go = rb ? 1 : 0;
+    }
     if (blockIdx.x == 0) {
-      Ctrl o = c;
-      o.rebuild = 0;
+      if (threadIdx.x < kSlots) next_vmax[threadIdx.x * kLineU64] = 0ull;
       if (rb) {
-        rebuild_adopt(o);
-        d.flags->max_nb = 0;
+        for (int k = threadIdx.x; k < kSlots * kLineInts; k += 64) d.flags->max_nb_slot[k] = 0;
+        const int nst = (d.ncell + kScanTile - 1) / kScanTile;
+        for (int k = threadIdx.x; k < nst; k += 64) d.scan_status[k] = 0ull;
       }
-      *next = o;
+      if (threadIdx.x == 0) {
+        Ctrl o = c;
+        o.rebuild = 0;
+        if (rb) rebuild_adopt(o);
+        *next = o;
+      }
     }
   }
   __syncthreads();
@@ -244,39 +257,80 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
   }
 }
 
-// (2) Exclusive scan of the cell counts into cell_start (one block); the
-// counts are cleared for the next binning pass.
+// (2) Exclusive scan of the cell counts into cell_start, one pass with
+// decoupled look-back: block b scans kScanTile cells (8 consecutive per
+// thread), publishes its total in status word b (flag 1), adds the totals of
+// its predecessors walking back until one has published its inclusive prefix
+// (flag 2), and publishes its own.  A word packs flag << 62 | value, so one
+// 64-bit atomic carries both.  Every block publishes its total before it
+// waits, and all blocks are resident at once (at most a few dozen), so every
+// wait ends; a bounded spin latches LE_E_STATE rather than hang.  The counts
+// are cleared for the next binning pass.
+__device__ __forceinline__ unsigned long long scan_word(int flag, long long v) {
+  return ((unsigned long long)flag << 62) | (unsigned long long)v;
+}
+
 __global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) {
   if (rebuild_off(d)) return;
   __shared__ int wsum[kScanBlock / 64];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
+  __shared__ long long base_sh;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c0 = 0; c0 < d.ncell; c0 += kScanBlock) {
-    const int c = c0 + threadIdx.x;
-    const int v = c < d.ncell ? d.cell_count[c] : 0;
-    int incl = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int woff = 0, tot = 0;
-    for (int w = 0; w < kScanBlock / 64; ++w) {
-      if (w < wid) woff += wsum[w];
-      tot += wsum[w];
-    }
-    if (c < d.ncell) {
-      d.cell_start[c] = carry + woff + incl - v;
-      d.cell_count[c] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
+  const int b = blockIdx.x;
+  const int c0 = b * kScanTile + 8 * threadIdx.x;
+  int v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = (c0 + u < d.ncell) ? d.cell_count[c0 + u] : 0;
+  int tot = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) tot += v[u];
+  int incl = tot;
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
   }
-  if (threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int woff = 0, agg = 0;
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    if (w < wid) woff += wsum[w];
+    agg += wsum[w];
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long* st = d.scan_status;
+    long long prefix = 0;
+    if (b == 0) {
+      __hip_atomic_store(&st[0], scan_word(2, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&st[b], scan_word(1, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int p = b - 1;
+      long long spins = 0;
+      while (p >= 0) {
+        const unsigned long long w = __hip_atomic_load(&st[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int flag = (int)(w >> 62);
+        if (flag == 0) {
+          if (++spins > (1ll << 24)) { latch(d.flags, LE_E_STATE); break; }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        prefix += (long long)(w & ((1ull << 62) - 1ull));
+        if (flag == 2) break;
+        --p;
+      }
+      __hip_atomic_store(&st[b], scan_word(2, prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    base_sh = prefix;
+  }
+  __syncthreads();
+  int run = (int)base_sh + woff + incl - tot;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (c0 + u < d.ncell) {
+      d.cell_start[c0 + u] = run;
+      d.cell_count[c0 + u] = 0;
+    }
+    run += v[u];
+  }
+  if (b == 0 && threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
 }
 
 // (3) Final slot = cell start + number of cell-mates with a smaller tag, so
@@ -636,6 +690,19 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
                           (double)sz2 * d.Lz, (double)sy2 * Delta))
           m_in |= 1u << u;
       }
+      if (!d.staged) {
+        // lists without a force-time halo: the partner's slot and image code
+        while (m_in) {
+          const int u = __builtin_ctz(m_in);
+          m_in &= m_in - 1u;
+          if (nog < K) {
+            d.nlo[idx4(nog, i, np)] = (uint32_t)d.halo_slot[hbase + h0 + u];
+            d.nlc[idx4(nog, i, np)] = d.halo_code[hbase + h0 + u];
+          }
+          ++nog;
+        }
+        continue;
+      }
       // append the accepted LDS indices into a ring of 16 per lane (rejected
       // ones go to the spare entry); a completed block of 8 leaves as one
       // 16-byte store
@@ -672,10 +739,16 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
       }
     }
   }
-  {  // telemetry: one atomic per wave
+  {  // telemetry: one atomic per block, spread over kSlots words
+    __shared__ int wmax[kTile / 64];
     int mx = npl + nog;
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(&d.flags->max_nb, mx);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kTile / 64; ++w) mx = max(mx, wmax[w]);
+      atomicMax(&d.flags->max_nb_slot[(blockIdx.x % kSlots) * kLineInts], mx);
+    }
   }
   if (!valid) return;
   int npl_p = (npl + kPlainBatch - 1) / kPlainBatch * kPlainBatch;
@@ -709,9 +782,17 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
 }
 
 // ---------------------------------------------------------- integrator
-__device__ __forceinline__ void vmax_commit(Ctrl* c, double v2) {
+// Block maximum of |c|^2 into one of the kSlots words; called by every
+// thread of the block.
+__device__ __forceinline__ void vmax_commit(const Dev& d, double v2) {
+  __shared__ double wm[kBlock / 64];
   double m = wave_max(v2);
-  if ((threadIdx.x & 63) == 0) atomicMax(&c->vmax_bits, (unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = fmax(m, wm[w]);
+    atomicMax(&d.vmax[(blockIdx.x % kSlots) * kLineU64], (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // Sum the per-block stress partials (fixed order) and write the stress
@@ -775,7 +856,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
     if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
   }
-  vmax_commit(c, v2);
+  vmax_commit(d, v2);
 }
 
 // ---------------------------------------------------------- force kernel
@@ -844,11 +925,12 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 //   kStepFused   as kStepLast, then the next half-kick and drift
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
-template <int MODE, bool MIXED, bool BONDS, bool SAMPLE>
+template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED>
 __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_out,
                                                  double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
-  __shared__ double hx[kHalo + 1], hy[kHalo + 1], hz[kHalo + 1];
+  constexpr int kH = STAGED ? kHalo + 1 : 1;  // no halo: every partner from global memory
+  __shared__ double hx[kH], hy[kH], hz[kH];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = d.flags->status;
@@ -867,7 +949,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
   // (sy Delta + sx L_x, sy L_y, sz L_z; the x image absorbs the offset's
   // wraps since the build).  A partner's displacement is then x_i - x_h.  All
   // slot loads, then all position loads, are in flight together.
-  {
+  if (STAGED) {
     const int nst = d.tile_nstage[lb];
     const int* hs = d.halo_slot + (size_t)lb * kHalo;
     const uint8_t* hc = d.halo_code + (size_t)lb * kHalo;
@@ -899,8 +981,8 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       }
     }
     if (threadIdx.x == 0) { hx[kHalo] = 1e100; hy[kHalo] = 1e100; hz[kHalo] = 1e100; }
+    __syncthreads();
   }
-  __syncthreads();
   double fx = 0.0, fy = 0.0, fz = 0.0;
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -909,7 +991,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
     // staged partners (already shifted to their image): one 16-byte index load
     // per batch of 8, two batches ahead
-    const int nb = d.n_plain[i] / kPlainBatch;
+    const int nb = STAGED ? d.n_plain[i] / kPlainBatch : 0;
     const uint4* __restrict__ l8 = reinterpret_cast<const uint4*>(d.nl16) + i;
     const uint4 zero4 = make_uint4(kHalo | (kHalo << 16), kHalo | (kHalo << 16), kHalo | (kHalo << 16),
                                    kHalo | (kHalo << 16));
@@ -938,21 +1020,32 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       v0 = v1;
       v1 = v2;
     }
-    // partners that were not staged: global memory, exact image arithmetic
-    const int nog = d.n_og[i];
+    // partners that were not staged: global memory, exact image arithmetic;
+    // eight gathers in flight, the next eight indices requested ahead
+    const int nbo = d.n_og[i] / kOtherBatch;
+    const int last_ob = d.K / kOtherBatch - 1;
     const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo) + i;
     const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc) + i;
-    for (int k = 0; k < nog; k += kOtherBatch) {
-      uint4 jv = l4[(size_t)(k / kOtherBatch) * np];
-      uint32_t cv = c4[(size_t)(k / kOtherBatch) * np];
-      uint32_t jj[4] = {jv.x, jv.y, jv.z, jv.w};
-      double4 pj[4];
+    uint4 jn0 = l4[0], jn1 = l4[(size_t)min(1, last_ob) * np];
+    uint32_t cn0 = c4[0], cn1 = c4[(size_t)min(1, last_ob) * np];
+    for (int b = 0; b < nbo; b += 2) {
+      const uint4 j0 = jn0, j1 = jn1;
+      const uint32_t c0 = cn0, c1 = cn1;
+      jn0 = l4[(size_t)min(b + 2, last_ob) * np];
+      jn1 = l4[(size_t)min(b + 3, last_ob) * np];
+      cn0 = c4[(size_t)min(b + 2, last_ob) * np];
+      cn1 = c4[(size_t)min(b + 3, last_ob) * np];
+      const bool second = b + 1 < nbo;  // entries of the second block are the list's
+      const uint32_t sl[8] = {j0.x, j0.y, j0.z, j0.w, second ? j1.x : (uint32_t)d.n,
+                              second ? j1.y : (uint32_t)d.n, second ? j1.z : (uint32_t)d.n,
+                              second ? j1.w : (uint32_t)d.n};
+      double4 pj[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pj[u] = P[jj[u]];
+      for (int u = 0; u < 8; ++u) pj[u] = P[sl[u]];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         int sx, sy, sz;
-        unpack_img((uint8_t)(cv >> (8 * u)), sx, sy, sz);
+        unpack_img((uint8_t)((u < 4 ? c0 : c1) >> (8 * (u & 3))), sx, sy, sz);
         sx += sy * W;
         double dy = (pi.y - pj[u].y) - (double)sy * d.Ly;
         double dx = ((pi.x - pj[u].x) - (double)sy * Delta) - (double)sx * d.Lx;
@@ -1042,7 +1135,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
     }
   }
-  if (MODE == kStepFused) vmax_commit(c, v2);
+  if (MODE == kStepFused) vmax_commit(d, v2);
   if (VIR) {
     double vals[kStressComps];
 #pragma unroll
@@ -1058,6 +1151,73 @@ __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
   __syncthreads();
   if (skip) return;
   reduce_partials(d, out6, virial_only != 0);
+}
+
+// ---------------------------------------------------------- observables
+// Per block: bin of each particle (its image in the box, with the matching
+// lab u_x), then one thread per bin sums the block's particles of that bin in
+// index order; kinetic and centre-of-mass sums by wave shuffles.  The final
+// kernel adds the block partials in block order.
+__global__ void __launch_bounds__(kBlock) k_obs_partial(Dev d, int nbins) {
+  __shared__ int sbin[kBlock];
+  __shared__ double sux[kBlock];
+  __shared__ double red[kBlock / 64][4];
+  if (d.flags->status) return;
+  const Ctrl* c = d.ctrl;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int np = d.np;
+  int b = -1;
+  double ux = 0.0, v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < d.n) {
+    const double4 p = reinterpret_cast<const double4*>(d.pos[c->pos_cur])[i];
+    const double* U = d.vel[c->aux_cur];
+    const double u0 = U[i], u1 = U[np + i], u2 = U[2 * np + i];
+    double y = p.y;
+    const double ky = wrap1(y, d.Ly);
+    ux = u0 - ky * d.sv;
+    b = (int)(y / d.Ly * (double)nbins);
+    if (b < 0) b = 0;
+    if (b > nbins - 1) b = nbins - 1;
+    const double cx = u0 - d.shear_rate * (p.y - 0.5 * d.Ly);
+    v[0] = d.mass * (cx * cx + u1 * u1 + u2 * u2);
+    v[1] = u0; v[2] = u1; v[3] = u2;
+  }
+  sbin[threadIdx.x] = b;
+  sux[threadIdx.x] = ux;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double t = v[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  const int stride = 2 * LE_MAX_BINS + 4;
+  double* out = d.obs_part + (size_t)blockIdx.x * stride;
+  for (int bb = threadIdx.x; bb < nbins; bb += kBlock) {
+    double cnt = 0.0, sum = 0.0;
+    for (int q = 0; q < kBlock; ++q)
+      if (sbin[q] == bb) { cnt += 1.0; sum += sux[q]; }
+    out[bb] = cnt;
+    out[nbins + bb] = sum;
+  }
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
+    out[2 * nbins + threadIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_obs_final(Dev d, int nbins, int nblk, double* out) {
+  if (d.flags->status) return;
+  const int stride = 2 * LE_MAX_BINS + 4;
+  for (int k = threadIdx.x; k < 2 * nbins + 4; k += kBlock) {
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += d.obs_part[(size_t)b * stride + k];
+    if (k == 2 * nbins) t = t / (3.0 * (double)d.n - 3.0);
+    else if (k > 2 * nbins) t = t / (double)d.n;
+    out[k] = t;
+  }
 }
 
 // ----------------------------------------------------------- state out
@@ -1132,13 +1292,15 @@ hipError_t launch_load_state(const Dev& d, hipStream_t s, const double* x0, cons
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild(const Dev& d, Ctrl* next, hipStream_t s, bool force, bool control) {
+hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vmax, hipStream_t s,
+                          bool force, bool control) {
   // kernels after the first see the control copy it writes
   Dev dn = d;
   dn.ctrl = next;
-  hipLaunchKernelGGL(k_control_bin, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, next, force ? 1 : 0,
-                     control ? 1 : 0);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, dn);
+  dn.vmax = next_vmax;
+  hipLaunchKernelGGL(k_control_bin, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, next, next_vmax,
+                     force ? 1 : 0, control ? 1 : 0);
+  hipLaunchKernelGGL(k_cell_scan, dim3((d.ncell + kScanTile - 1) / kScanTile), dim3(kScanBlock), 0, s, dn);
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
   hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(kTile), 0, s, dn);
   return hipGetLastError();
@@ -1148,18 +1310,23 @@ hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE, bool SAMPLE>
-static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so) {
+template <int MODE, bool SAMPLE, bool STAGED>
+static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so) {
   dim3 g(d.ntiles), b(kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, true, true, SAMPLE>), g, b, 0, s, d, f_out, so);
-    else hipLaunchKernelGGL((k_force<MODE, true, false, SAMPLE>), g, b, 0, s, d, f_out, so);
+    if (bonds) hipLaunchKernelGGL((k_force<MODE, true, true, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
+    else hipLaunchKernelGGL((k_force<MODE, true, false, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
   } else {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, false, true, SAMPLE>), g, b, 0, s, d, f_out, so);
-    else hipLaunchKernelGGL((k_force<MODE, false, false, SAMPLE>), g, b, 0, s, d, f_out, so);
+    if (bonds) hipLaunchKernelGGL((k_force<MODE, false, true, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
+    else hipLaunchKernelGGL((k_force<MODE, false, false, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
   }
+}
+template <int MODE, bool SAMPLE>
+static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so) {
+  if (d.staged) launch_force_s<MODE, SAMPLE, true>(d, s, f_out, so);
+  else launch_force_s<MODE, SAMPLE, false>(d, s, f_out, so);
 }
 
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
@@ -1184,6 +1351,12 @@ hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool v
   return hipGetLastError();
 }
 
+hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out) {
+  const int nblk = blocks_for(d.n);
+  hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kBlock), 0, s, d, nbins);
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kBlock), 0, s, d, nbins, nblk, out);
+  return hipGetLastError();
+}
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,
                             int32_t* order) {
   hipLaunchKernelGGL(k_state_out, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, x, u, cell_of, order);

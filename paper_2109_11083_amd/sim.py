@@ -152,6 +152,18 @@ class Sim:
         self.sync()
         return s.cpu().numpy()
 
+    def observables(self, nbins: int = 50, out: torch.Tensor | None = None, host: bool = True):
+        """y-profiles of count and summed u_x, kinetic kT and CoM velocity of the current state."""
+        if out is None:
+            out = torch.empty(2 * nbins + 4, dtype=torch.float64, device=self.device)
+        B.le_observables(self.handle, nbins, out.data_ptr())
+        if not host:
+            return out
+        self.sync()
+        o = out.cpu().numpy()
+        return dict(count=o[:nbins], sum_ux=o[nbins:2 * nbins], kT=float(o[2 * nbins]),
+                    com=o[2 * nbins + 1:2 * nbins + 4])
+
     def state(self):
         n = self.params.n
         x = torch.empty((3, n), dtype=torch.float64, device=self.device)

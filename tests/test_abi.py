@@ -67,6 +67,10 @@ def test_workspace_bytes_and_geometry_errors():
     with pytest.raises(B.LeError) as e:
         B.le_workspace_bytes(_lj(n_chains=100, chain_len=20).to_c())  # 2000 > n
     assert e.value.code == B.LE_E_ARG
+    for t in (-1, 3):
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(_lj(tune=t).to_c())
+        assert e.value.code == B.LE_E_ARG
 
 
 def test_init_rejects_small_workspace_before_any_device_work():

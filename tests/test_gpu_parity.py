@@ -160,25 +160,30 @@ def _forces_case(w_x, w_u, p: Params, step0, tol_f, tol_w, method=0):
     return ef, ew
 
 
+# tune: 0 = layout chosen from density, 1 = LDS halo, 2 = partners from global memory
+@pytest.mark.parametrize("tune", [0, 2])
 @pytest.mark.parametrize("frac", [0.0, 0.3, 0.999])
-def test_forces_fp64_lj(frac):
-    w, p = _lj_case()
+def test_forces_fp64_lj(frac, tune):
+    w, p = _lj_case(tune=tune)
     _forces_case(w.x, w.u, p, _step0_for_fraction(p, frac), 1e-12, 1e-12)
 
 
+@pytest.mark.parametrize("tune", [0, 2])
 @pytest.mark.parametrize("frac", [0.0, 0.6])
-def test_forces_mixed_lj(frac):
-    w, p = _lj_case(precision="mixed")
+def test_forces_mixed_lj(frac, tune):
+    w, p = _lj_case(precision="mixed", tune=tune)
     _forces_case(w.x, w.u, p, _step0_for_fraction(p, frac), 1e-5, 1e-4)
 
 
-def test_forces_fp64_kg_fene():
-    w, p = _kg_case()
+@pytest.mark.parametrize("tune", [0, 1, 2])
+def test_forces_fp64_kg_fene(tune):
+    w, p = _kg_case(tune=tune)
     _forces_case(w.x, w.u, p, 777, 1e-12, 1e-12)
 
 
-def test_forces_mixed_kg():
-    w, p = _kg_case(precision="mixed")
+@pytest.mark.parametrize("tune", [0, 1])
+def test_forces_mixed_kg(tune):
+    w, p = _kg_case(precision="mixed", tune=tune)
     _forces_case(w.x, w.u, p, 777, 1e-5, 1e-4)
 
 
@@ -227,9 +232,9 @@ def test_ideal_gas_trajectory_bitwise_skin0():
     sim.close()
 
 
-@pytest.mark.parametrize("skin", [0.0, 0.3])
-def test_lj_trajectory_100_steps(skin):
-    w, p = _lj_case(shear_rate=0.5, skin=skin)
+@pytest.mark.parametrize("skin,tune", [(0.0, 0), (0.3, 0), (0.3, 2)])
+def test_lj_trajectory_100_steps(skin, tune):
+    w, p = _lj_case(shear_rate=0.5, skin=skin, tune=tune)
     sim = Sim(p, w.x, w.u, step0=0)
     ref = O.Sim(w.x, w.u, _oracle_params(p), step0=0)
     ring = sim.step(100, sample_every=10)
@@ -275,6 +280,40 @@ def test_determinism_and_exact_restart():
         s.close()
 
 
+def _check_observables(got, ref, tag):
+    assert np.array_equal(got["count"], ref["count"]), tag
+    scale = max(np.abs(ref["sum_ux"]).max(), 1.0)
+    assert np.abs(got["sum_ux"] - ref["sum_ux"]).max() / scale < 1e-12, tag
+    assert abs(got["kT"] - ref["kT"]) / ref["kT"] < 1e-12, tag
+    assert np.abs(got["com"] - ref["com"]).max() < 1e-12 * max(1.0, np.abs(ref["com"]).max() * 1e3), tag
+
+
+@pytest.mark.parametrize("nbins", [1, 50, 256])
+def test_observables_mid_run(nbins):
+    """y-profiles, kinetic temperature and CoM velocity of a state whose
+    pending boundary crossings are not yet applied (lazy wrap between
+    rebuilds) against the oracle on the same state."""
+    w, p = _lj_case(shear_rate=0.5, skin=0.3)
+    sim = Sim(p, w.x, w.u, step0=0)
+    sim.step(37)
+    got = sim.observables(nbins)
+    x, u, f, step = sim.state()
+    ref = O.observables(x, u, 0.0, _oracle_params(p), nbins=nbins)
+    assert got["count"].sum() == p.n
+    _check_observables(got, ref, nbins)
+    sim.close()
+
+
+def test_observables_rejects_bad_bins():
+    w, p = _lj_case()
+    sim = Sim(p, w.x, w.u)
+    for nb in (0, B.LE_MAX_BINS + 1):
+        with pytest.raises(B.LeError) as e:
+            sim.observables(nb)
+        assert e.value.code == B.LE_E_ARG
+    sim.close()
+
+
 # ------------------------------------------------------------------ errors
 def test_bond_break_is_latched():
     x = np.array([[1.0, 2.6, 5.0, 7.0], [5.0, 5.0, 5.0, 5.0], [5.0, 5.0, 5.0, 5.0]])
@@ -312,9 +351,10 @@ def test_neighbor_capacity_is_latched():
 
 # ------------------------------------------------------------------ full-size samples
 def test_full_size_lj_256k_sampled():
-    """The 256,000-particle LJ system at its real size: cells bit-exact, pair
-    set at r_list bit-exact, forces at 400 sampled particles within 1e-12."""
-    w = inputs.lj_workload(n_side=64, shear_rate=0.1, seed=21)
+    """The 256,000-particle LJ system at its real size (the benchmarked
+    configuration): cells bit-exact, pair set at r_list bit-exact, forces at
+    400 sampled particles within 1e-12, observables."""
+    w = inputs.lj_workload(n=256000, shear_rate=0.1, seed=21)
     p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.1, seed=21)
     step0 = 7777
     sim = Sim(p, w.x, w.u, step0=step0)
@@ -336,5 +376,35 @@ def test_full_size_lj_256k_sampled():
     rms = math.sqrt(float((Fs ** 2).sum(axis=1).mean()))
     err = float(np.sqrt(((F[:, idx].T - Fs) ** 2).sum(axis=1)).max()) / rms
     _log(f"256k sampled e_F={err:.3e}")
+    assert err <= 1e-12
+    _check_observables(sim.observables(50), O.observables(xw, uw, Delta, op, nbins=50), "256k")
+    sim.close()
+
+
+def test_full_size_kg_400k_sampled():
+    """The Kremer-Grest melt at its benchmarked size (2000 chains x 200 beads,
+    WCA + FENE): cells bit-exact, pair set at r_list bit-exact, forces with
+    bonds at 300 sampled beads within 1e-12."""
+    w, p = _kg_case(n_chains=2000, chain_len=200, shear_rate=0.01)
+    step0 = 4321
+    sim = Sim(p, w.x, w.u, step0=step0)
+    out = sim.build_cells()
+    op = _oracle_params(p)
+    Delta = O.offset(step0, p.dt, p.shear_rate, p.box[0], p.box[1])
+    xw, uw = O.le_wrap(w.x, w.u, Delta, op)
+    nc = tuple(int(math.floor(p.box[a] / (p.rlist * (1 + 1e-9)))) for a in range(3))
+    cref, oref = O.cells(xw, nc, p.box)
+    assert np.array_equal(out["cell_of"], cref) and np.array_equal(out["order"], oref)
+    ref = O.pairs_cells(xw, Delta, p.box, p.rlist)
+    key = lambda a: np.sort(np.minimum(a[:, 0], a[:, 1]).astype(np.int64) * p.n + np.maximum(a[:, 0], a[:, 1]))
+    assert np.array_equal(key(out["pairs"]), key(ref))
+    F, W = sim.forces()
+    rng = np.random.default_rng(3)
+    ys = np.argsort(xw[1])
+    idx = np.concatenate([ys[:75], ys[-75:], rng.choice(p.n, 150, replace=False)])
+    Fs = O.forces_sample(xw, Delta, op, idx)
+    rms = math.sqrt(float((Fs ** 2).sum(axis=1).mean()))
+    err = float(np.sqrt(((F[:, idx].T - Fs) ** 2).sum(axis=1)).max()) / rms
+    _log(f"kg 400k sampled e_F={err:.3e}")
     assert err <= 1e-12
     sim.close()
