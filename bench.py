@@ -63,8 +63,21 @@ def kg_params(shear_rate, precision, seed=31, skin=0.3, n_chains=KG_CHAINS, chai
     return w, p
 
 
-def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=True, skin=0.3,
+def pick_skin(n, shear_rate, precision, workload):
+    """Autotuned skin for a workload (short bursts; see paper_2109_11083_amd.tune)."""
+    from paper_2109_11083_amd.tune import autotune
+    if workload == "kg":
+        w, p = kg_params(shear_rate, precision)
+    else:
+        w, p = lj_params(n, shear_rate, precision)
+    best, table = autotune(p, w.x, w.u)
+    return best.skin, [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
+
+
+def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=0x1, skin=0.3,
             workload="lj"):
+    """One timed run.  timing: phase mask for HIP-event timing inside the timed
+    region (bit 0: the plain-step force kernel; 0xF: every phase)."""
     import torch
     from paper_2109_11083_amd import binding as B
     from paper_2109_11083_amd.sim import Sim
@@ -133,21 +146,49 @@ def cpu_baseline(n, shear_rate, nsteps):
                        f"1 thread, {t1 - t0:.1f} s)")
 
 
+def kernel_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2109_11083_amd", "csrc", "le_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(name):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary
+    (profiles/<name>.md), or None if it was taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("le_kernels.hip sha256 prefix") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--shear-rate", type=float, default=0.1)
+    ap.add_argument("--shear-rate", type=float, default=None,
+                    help="default 0.1 (LJ) / 0.01 (KG)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--n", type=int, default=256000,
-                    help="particles: n sites of a ceil(n^(1/3))^3 lattice (256000 -> 64^3)")
+                    help="LJ particles: n sites of a ceil(n^(1/3))^3 lattice (256000 -> 64^3)")
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events in the timed region (then no per-kernel roofline)")
-    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--skin", default="auto",
+                    help="neighbour-list skin, or 'auto' (autotuned per workload, short bursts)")
     ap.add_argument("--workload", default="lj", choices=["lj", "kg"],
                     help="lj: 256,000-particle LJ fluid (the headline); kg: 2000 x 200 Kremer-Grest melt")
     ap.add_argument("--copy-probe", action="store_true",
@@ -163,57 +204,98 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    log(f"bench: {args.workload} n={args.n} shear_rate={args.shear_rate} {args.precision} "
-        f"steps={args.steps} warmup={args.warmup}")
-    r = run_gpu(args.n, args.shear_rate, args.precision, args.steps, args.warmup,
-                timing=not args.no_timing, skin=args.skin, workload=args.workload)
-    log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
-        f"rebuilds={r['rebuilds']}, phases={r['phases']}")
+    kg = args.workload == "kg"
+    sr = args.shear_rate if args.shear_rate is not None else (0.01 if kg else 0.1)
 
+    tune_table = None
+    if args.skin == "auto":
+        skin, tune_table = pick_skin(args.n, sr, args.precision, args.workload)
+        log(f"bench: autotuned skin {skin}: {tune_table}")
+    else:
+        skin = float(args.skin)
+    args.skin = skin
+    size = f"{KG_CHAINS}x{KG_LEN}" if kg else f"n={args.n}"
+    log(f"bench: {args.workload} {size} shear_rate={sr} {args.precision} "
+        f"steps={args.steps} warmup={args.warmup} skin={skin}")
+    r = run_gpu(args.n, sr, args.precision, args.steps, args.warmup,
+                timing=0 if args.no_timing else 0x1, skin=args.skin, workload=args.workload)
+    log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
+        f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
+
+    # roofline of the dominant kernel: the fused force / thermostat / integrator
+    # kernel of plain steps (timing phase 0), from its event-timed average
     force_ms, force_n = r["phases"]["force"]
     roofline = None
+    kname = ("k_force_kg400k_" if kg else "k_force_lj256k_") + args.precision
     if force_n > 0:
-        avg_force_s = force_ms / 1e3 / force_n
-        rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
-        pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
-        flops_pp = PAIR_FLOPS * pairs_pp / 2.0 + STEP_FLOPS
-        achieved = r["n"] * flops_pp / avg_force_s / 1e12
-        roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS,
-                        unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=None,
-                        kernel="k_force (fused pair force + Langevin + velocity Verlet)",
-                        avg_kernel_us=round(avg_force_s * 1e6, 3),
-                        flops_per_particle=round(flops_pp, 1))
+        avg_s = force_ms / 1e3 / force_n
+        traffic = read_traffic(kname + "_traffic")
+        if kg:
+            # HBM-bound: algorithmic bytes of the fused step per particle
+            achieved = r["n"] * BYTES_FUSED / avg_s / 1e9
+            roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                            frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic,
+                            bytes_per_particle=BYTES_FUSED)
+        else:
+            rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
+            pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
+            flops_pp = PAIR_FLOPS * pairs_pp / 2.0 + STEP_FLOPS
+            achieved = r["n"] * flops_pp / avg_s / 1e12
+            roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS,
+                            unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=traffic,
+                            flops_per_particle=round(flops_pp, 1))
+        roofline.update(kernel="k_force (fused pair force + Langevin + velocity Verlet), plain steps",
+                        avg_kernel_us=round(avg_s * 1e6, 3), launches=force_n,
+                        hbm_GBs_if_traffic=(round(traffic / avg_s / 1e9, 1) if traffic else None))
 
     extra = {}
+    # per-phase device time of the same workload (all phases event-timed; a separate, shorter run)
+    b = run_gpu(args.n, sr, args.precision, min(args.steps, 2000), 100, timing=0xF, skin=args.skin,
+                workload=args.workload)
+    extra["phase_us_per_step"] = {k: round(1e3 * v[0] / b["steps"], 2) for k, v in b["phases"].items()}
+    log(f"bench: phases {extra['phase_us_per_step']}")
     if not args.no_extra:
-        for sr in (0.01, 1.0):
-            e = run_gpu(args.n, sr, args.precision, 2000, 100, skin=args.skin)
-            extra[f"lj_shear_rate_{sr}"] = dict(value=e["value"], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
-                                                eta=e["eta"])
-            log(f"bench: shear_rate={sr}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
-        # mixed vs FP64 on the same workload: throughput and viscosity with its error bar
+        if not kg:
+            for sr2 in (0.01, 1.0):
+                e = run_gpu(args.n, sr2, args.precision, 2000, 100, skin=args.skin)
+                extra[f"lj_shear_rate_{sr2}"] = dict(value=e["value"],
+                                                    rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
+                                                    eta=e["eta"])
+                log(f"bench: shear_rate={sr2}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
+        # the other precision on the same workload: throughput and viscosity with its error bar
         other = "mixed" if args.precision == "fp64" else "fp64"
-        m = run_gpu(args.n, args.shear_rate, other, args.steps, args.warmup, skin=args.skin)
+        m = run_gpu(args.n, sr, other, args.steps, args.warmup, skin=args.skin, workload=args.workload)
         fm, fn = m["phases"]["force"]
-        extra[f"lj_{other}"] = dict(value=m["value"], force_kernel_us=1e3 * fm / max(fn, 1),
-                                    eta=m["eta"], eta_se=m["eta_se"],
-                                    eta_diff_vs_main=(m["eta"] - r["eta"]) if r["eta"] is not None else None)
+        extra[f"{args.workload}_{other}"] = dict(
+            value=m["value"], force_kernel_us=1e3 * fm / max(fn, 1), eta=m["eta"], eta_se=m["eta_se"],
+            eta_diff_vs_main=(m["eta"] - r["eta"]) if (r["eta"] is not None and m["eta"] is not None)
+            else None)
         log(f"bench: {other}: {m['value']:.4e} p-steps/s eta={m['eta']}")
-        # Kremer-Grest melt, 2000 chains x 200 beads (HBM-bound pair kernel)
-        k = run_gpu(0, 0.01, args.precision, 2000, 100, skin=args.skin, workload="kg")
-        kf, kn = k["phases"]["force"]
-        kus = 1e3 * kf / max(kn, 1)
-        extra["kg_2000x200"] = dict(value=k["value"], force_kernel_us=kus,
-                                    force_kernel_GBs_algorithmic=k["n"] * BYTES_FUSED / (kus * 1e-6) / 1e9,
-                                    rebuilds_per_1000=1000 * k["rebuilds"] / 2000, eta=k["eta"],
-                                    shear_rate=0.01)
-        log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
+        if not kg:
+            # Kremer-Grest melt, 2000 chains x 200 beads (HBM-bound pair kernel)
+            kskin, _ = pick_skin(0, 0.01, args.precision, "kg")
+            k = run_gpu(0, 0.01, args.precision, 2000, 100, skin=kskin, workload="kg")
+            kf, kn = k["phases"]["force"]
+            kus = 1e3 * kf / max(kn, 1)
+            extra["kg_2000x200"] = dict(value=k["value"], force_kernel_us=kus,
+                                        force_kernel_GBs_algorithmic=k["n"] * BYTES_FUSED / (kus * 1e-6) / 1e9,
+                                        rebuilds_per_1000=1000 * k["rebuilds"] / 2000, shear_rate=0.01,
+                                        skin=kskin)
+            log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
 
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.n, args.shear_rate, args.cpu_steps)
+    if not args.no_cpu_baseline and not kg:
+        cpu = cpu_baseline(args.n, sr, args.cpu_steps)
         log(f"bench: cpu oracle {cpu['value']:.4e} particle-steps/s")
 
+    if kg:
+        wl = (f"Kremer-Grest melt {KG_CHAINS} chains x {KG_LEN} beads (N={r['n']}), density 0.85, "
+              f"WCA + FENE(30, 1.5), T=1, Langevin gamma=0.5 on peculiar velocity, shear_rate={sr}, "
+              f"dt=0.01, skin {args.skin}, {args.precision}; overlap-free lattice-path start")
+    else:
+        wl = (f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
+              f"T=1, Langevin gamma=1 on peculiar velocity, shear_rate={sr}, "
+              f"dt=0.005, skin {args.skin}, {args.precision}")
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -228,11 +310,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
-            "workload": f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
-                        f"T=1, Langevin gamma=1 on peculiar velocity, shear_rate={args.shear_rate}, "
-                        f"dt=0.005, skin {args.skin}, {args.precision}",
+            "workload": wl,
             "n_particles": r["n"],
-            "shear_rate": args.shear_rate,
+            "shear_rate": sr,
             "precision": args.precision,
             "stress_sample_every": 10,
             "skin": args.skin,
@@ -240,7 +320,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "rebuilds_per_1000_steps": round(1000.0 * r["rebuilds"] / args.steps, 2),
-        "phase_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()},
+        "skin_autotune": tune_table,
         "viscosity": {"eta": r["eta"], "block_se": r["eta_se"], "window": "last 20% of the timed steps"},
         "ux_profile_50_bins": [round(v, 5) for v in r["ux_profile"]],
         "kT_kinetic": r["kT"],

@@ -182,14 +182,16 @@ le_status le_sync(le_sim* s);
  * le_init and the largest neighbour count seen at the last rebuild. */
 le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors);
 
-/* Phase timing: while enabled, le_step records a pair of HIP events on the
- * simulation's stream around each launch group and accumulates the elapsed
- * device time per phase: 0 the force kernel (pair + bond forces, thermostat
- * and integrator, fused), 1 the rebuild chain (crossing/wrap, sort, stencil,
- * neighbour lists; empty launches on steps without a rebuild), 2 step
- * bookkeeping (offset, rebuild decision, first half-kick), 3 the stress
- * reduction.  le_timing_enable(s, 1) resets the totals; creating events is
- * the only host-side resource it takes. */
+/* Phase timing: le_step records a pair of HIP events on the simulation's
+ * stream around each launch group of an enabled phase and accumulates the
+ * elapsed device time per phase: 0 the fused force kernel (pair + bond
+ * forces, thermostat and integrator) of plain steps, 1 the rebuild chain
+ * (crossing/wrap, sort, stencil, neighbour lists; empty launches on steps
+ * without a rebuild), 2 the first half-kick of a call, 3 sampled steps (the
+ * force kernel with the virial, then the stress reduction).  enabled is a bit
+ * mask over the phases (bit k: phase k; 0 switches timing off, 0xF times
+ * all); enabling resets the totals.  Creating events is the only host-side
+ * resource it takes. */
 le_status le_timing_enable(le_sim* s, int32_t enabled);
 
 /* Totals since the last enable (waits for the stream): ms[4] elapsed device

@@ -187,8 +187,13 @@ def le_observables(sim: int, nbins: int, out: int) -> None:
     check(lib().le_observables(sim, nbins, out), "le_observables")
 
 
-def le_timing_enable(sim: int, enabled: bool) -> None:
-    check(lib().le_timing_enable(sim, 1 if enabled else 0), "le_timing_enable")
+def le_timing_enable(sim: int, phases) -> None:
+    """phases: bit mask over PHASES (True = all, False = off)."""
+    if phases is True:
+        phases = 0xF
+    elif phases is False:
+        phases = 0
+    check(lib().le_timing_enable(sim, int(phases)), "le_timing_enable")
 
 
 PHASES = ("force", "rebuild", "bookkeeping", "stress")

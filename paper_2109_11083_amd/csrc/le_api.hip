@@ -21,7 +21,7 @@ struct le_sim {
   unsigned long long* counter;         // device scratch counter (pairs_out)
   double* scratch6;                    // device 6 doubles
   // phase timing (le_timing_enable)
-  bool timing;
+  int32_t timing;                      // bit k: time phase k
   std::vector<hipEvent_t> ev;          // pairs (start, stop)
   std::vector<int> ev_phase;           // phase of each recorded pair
   size_t ev_used;                      // pairs recorded and not yet folded
@@ -225,7 +225,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
 
 le_status hip_check(hipError_t e) { return e == hipSuccess ? LE_OK : LE_E_HIP; }
 
-constexpr size_t kMaxEventPairs = 4096;
+constexpr size_t kMaxEventPairs = 16384;
 
 // Fold recorded event pairs into the per-phase totals (waits for the stream).
 le_status fold_events(le_sim* s) {
@@ -241,9 +241,10 @@ le_status fold_events(le_sim* s) {
   return LE_OK;
 }
 
-// Record the start of a timed launch group; returns the pair index or -1.
-long begin_phase(le_sim* s, int phase) {
-  if (!s->timing) return -1;
+// Reserve an event pair for a timed launch of `phase`; returns its index or
+// -1 when the phase is not timed.
+long reserve_pair(le_sim* s, int phase) {
+  if (!((s->timing >> phase) & 1)) return -1;
   if (s->ev_used == kMaxEventPairs && fold_events(s) != LE_OK) return -1;
   size_t k = s->ev_used;
   if (s->ev.size() < 2 * (k + 1)) {
@@ -255,8 +256,15 @@ long begin_phase(le_sim* s, int phase) {
     s->ev_phase.push_back(0);
   }
   s->ev_phase[k] = phase;
-  if (hipEventRecord(s->ev[2 * k], s->stream) != hipSuccess) return -1;
   return (long)k;
+}
+
+// Record the start of a timed launch group; returns the pair index or -1.
+long begin_phase(le_sim* s, int phase) {
+  long k = reserve_pair(s, phase);
+  if (k < 0) return -1;
+  if (hipEventRecord(s->ev[2 * k], s->stream) != hipSuccess) return -1;
+  return k;
 }
 
 void end_phase(le_sim* s, long k) {
@@ -309,7 +317,7 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   le_sim* s = new (std::nothrow) le_sim();
   if (!s) return LE_E_ARG;
   s->host_status = 0;
-  s->timing = false;
+  s->timing = 0;
   s->ev_used = 0;
   for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
   s->p = *p;
@@ -386,15 +394,24 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
     const bool last = (k == nsteps);
     const bool sample = sample_every > 0 && (k % sample_every) == 0;
-    ev = begin_phase(s, 0);
-    st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, sample, nullptr, nullptr));
-    end_phase(s, ev);
-    if (st == LE_OK && sample) {
-      double* slot = stress_ring + 6 * (ns % ring_cap);
-      ++ns;
+    // phase 0: the fused force kernel of plain steps, timed by the dispatch
+    // itself; phase 3: sampled steps (force kernel with the virial, then the
+    // stress reduction)
+    if (sample) {
       ev = begin_phase(s, 3);
-      st = hip_check(launch_stress_final(d, q, slot, false));
+      st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, true, nullptr, nullptr));
+      if (st == LE_OK) {
+        double* slot = stress_ring + 6 * (ns % ring_cap);
+        ++ns;
+        st = hip_check(launch_stress_final(d, q, slot, false));
+      }
       end_phase(s, ev);
+    } else {
+      ev = reserve_pair(s, 0);
+      st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, false, nullptr, nullptr,
+                                  ev >= 0 ? s->ev[2 * ev] : nullptr,
+                                  ev >= 0 ? s->ev[2 * ev + 1] : nullptr));
+      if (ev >= 0) s->ev_used = (size_t)ev + 1;
     }
     if (st == LE_OK && !last) {
       ev = begin_phase(s, 1);
@@ -455,7 +472,7 @@ le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors) {
 le_status le_timing_enable(le_sim* s, int32_t enabled) {
   if (!s) return LE_E_ARG;
   le_status st = fold_events(s);
-  s->timing = enabled != 0;
+  s->timing = enabled & 0xF;
   for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
   return st;
 }

@@ -139,7 +139,7 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
                           bool force, bool control);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
-                        double* sample_out);
+                        double* sample_out, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
 hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out);
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,

@@ -14,6 +14,8 @@
 //                   k-th entries of 64 consecutive particles are contiguous)
 #include <math.h>
 
+#include <hip/hip_ext.h>
+
 #include "le_internal.h"
 
 namespace le {
@@ -1310,37 +1312,41 @@ hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The force launches go through hipExtLaunchKernelGGL so that optional
+// events (e0, e1) take the timestamps of the dispatch itself.
 template <int MODE, bool SAMPLE, bool STAGED>
-static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so) {
+static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
+                           hipEvent_t e1) {
   dim3 g(d.ntiles), b(kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, true, true, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
-    else hipLaunchKernelGGL((k_force<MODE, true, false, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
+    if (bonds) hipExtLaunchKernelGGL((k_force<MODE, true, true, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
+    else hipExtLaunchKernelGGL((k_force<MODE, true, false, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
   } else {
-    if (bonds) hipLaunchKernelGGL((k_force<MODE, false, true, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
-    else hipLaunchKernelGGL((k_force<MODE, false, false, SAMPLE, STAGED>), g, b, 0, s, d, f_out, so);
+    if (bonds) hipExtLaunchKernelGGL((k_force<MODE, false, true, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
+    else hipExtLaunchKernelGGL((k_force<MODE, false, false, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
   }
 }
 template <int MODE, bool SAMPLE>
-static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so) {
-  if (d.staged) launch_force_s<MODE, SAMPLE, true>(d, s, f_out, so);
-  else launch_force_s<MODE, SAMPLE, false>(d, s, f_out, so);
+static void launch_force_t(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
+                           hipEvent_t e1) {
+  if (d.staged) launch_force_s<MODE, SAMPLE, true>(d, s, f_out, so, e0, e1);
+  else launch_force_s<MODE, SAMPLE, false>(d, s, f_out, so, e0, e1);
 }
 
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
-                        double* sample_out) {
+                        double* sample_out, hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case kForcesOnly: launch_force_t<kForcesOnly, false>(d, s, f_out, nullptr); break;
-    case kInitForce: launch_force_t<kInitForce, false>(d, s, f_out, nullptr); break;
+    case kForcesOnly: launch_force_t<kForcesOnly, false>(d, s, f_out, nullptr, e0, e1); break;
+    case kInitForce: launch_force_t<kInitForce, false>(d, s, f_out, nullptr, e0, e1); break;
     case kStepLast:
-      if (sample) launch_force_t<kStepLast, true>(d, s, f_out, sample_out);
-      else launch_force_t<kStepLast, false>(d, s, f_out, nullptr);
+      if (sample) launch_force_t<kStepLast, true>(d, s, f_out, sample_out, e0, e1);
+      else launch_force_t<kStepLast, false>(d, s, f_out, nullptr, e0, e1);
       break;
     case kStepFused:
-      if (sample) launch_force_t<kStepFused, true>(d, s, f_out, sample_out);
-      else launch_force_t<kStepFused, false>(d, s, f_out, nullptr);
+      if (sample) launch_force_t<kStepFused, true>(d, s, f_out, sample_out, e0, e1);
+      else launch_force_t<kStepFused, false>(d, s, f_out, nullptr, e0, e1);
       break;
   }
   return hipGetLastError();

@@ -1,0 +1,47 @@
+"""Throughput autotuner for the neighbour-list skin and the pair-kernel layout.
+
+The physics does not depend on either choice (the lists always hold every
+pair within r_c + skin, and the rebuild criterion keeps them complete); only
+the split of time between list builds and pair work does.  Each candidate is
+run for a short burst from the same start on the caller's device and the
+fastest is returned.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import torch
+
+from .sim import Params, Sim
+
+
+def autotune(p: Params, x0, u0, skins=(0.2, 0.3, 0.4, 0.5, 0.6, 0.8), tunes=(0,), steps=400,
+             warmup=100, step0=0):
+    """Return (best Params, table of (skin, tune, particle-steps/s))."""
+    table = []
+    best = None
+    for tune in tunes:
+        for skin in skins:
+            q = dataclasses.replace(p, skin=float(skin), tune=int(tune))
+            try:
+                sim = Sim(q, x0, u0, step0=step0)
+            except Exception:  # geometry not valid for this skin (too few cells)
+                continue
+            try:
+                sim.step(warmup)
+                sim.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step(steps)
+                sim.sync()
+                t1 = time.perf_counter()
+            finally:
+                sim.close()
+            rate = q.n * steps / (t1 - t0)
+            table.append((float(skin), int(tune), rate))
+            if best is None or rate > best[2]:
+                best = (float(skin), int(tune), rate)
+    if best is None:
+        raise RuntimeError("no candidate layout is valid for this system")
+    return dataclasses.replace(p, skin=best[0], tune=best[1]), table
