@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -131,6 +133,31 @@ def copy_probe(mib=1024, reps=5):
           flush=True)
 
 
+def serving_bench(count=64):
+    """Sweep requests (N ~ U{2000..64000}, shear rate log-uniform in [1e-3, 1], 5000 steps,
+    Poisson arrivals at 4/s): continuous batching in mixed precision against FP64 one request at a
+    time (FIFO), on the same trace; plus the same requests all at once (sweep throughput)."""
+    from paper_2109_11083_amd.serve import Server, sweep_trace
+    out = {}
+    runs = [("batched_mixed", "mixed", 16, False), ("fifo_fp64", "fp64", 1, False),
+            ("batched_mixed_burst", "mixed", 16, True), ("fifo_fp64_burst", "fp64", 1, True)]
+    etas = {}
+    for name, prec, slots, burst in runs:
+        trace = sweep_trace(count=count, precision=prec, burst=burst)
+        res, summ = Server(max_active=slots).run(trace, realtime=not burst)
+        etas[name] = np.array([r.eta for r in res])
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"bench: serving {name}: p50 {summ['p50_s']:.3f} s p99 {summ['p99_s']:.3f} s "
+            f"throughput {summ['throughput']:.3e} particle-steps/s")
+    d = np.abs(etas["batched_mixed"] - etas["fifo_fp64"])
+    out["eta_mixed_vs_fp64"] = dict(median_abs_diff=float(np.median(d)), max_abs_diff=float(d.max()),
+                                    note="per request, 5000 steps; differences are dominated by the "
+                                         "statistical error of short runs, not by the precision")
+    out["trace"] = dict(requests=count, n="U{2000..64000}", shear_rate="log-U[1e-3, 1]", steps=5000,
+                        arrivals="Poisson 4/s (burst: all at t=0)", skin=0.4)
+    return out
+
+
 def cpu_baseline(n, shear_rate, nsteps):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
@@ -191,6 +218,9 @@ def main():
                     help="neighbour-list skin, or 'auto' (autotuned per workload, short bursts)")
     ap.add_argument("--workload", default="lj", choices=["lj", "kg"],
                     help="lj: 256,000-particle LJ fluid (the headline); kg: 2000 x 200 Kremer-Grest melt")
+    ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
+                    help="shear-rate sweep serving: p50/p99 time-to-result and sweep throughput")
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
     args = ap.parse_args()
@@ -282,6 +312,9 @@ def main():
                                         rebuilds_per_1000=1000 * k["rebuilds"] / 2000, shear_rate=0.01,
                                         skin=kskin)
             log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
+
+    if args.serve and not kg:
+        extra["serving"] = serving_bench(args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline and not kg:

@@ -59,6 +59,7 @@ extern "C" {
 #endif
 
 typedef struct le_sim le_sim;
+typedef struct le_graph le_graph;
 typedef int32_t le_status;
 
 #define LE_OK 0
@@ -174,6 +175,25 @@ le_status le_observables(le_sim* s, int32_t nbins, double* out);
  * continues the run exactly.  Waits for the stream and returns any latched
  * device error. */
 le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step);
+
+/* A HIP graph of le_step(s, nsteps, sample_every, stress_ring, ring_cap),
+ * captured once on the simulation's stream so that a chunk of steps costs
+ * one launch on the host.  nsteps must be even (each step alternates the
+ * device control copy, so an even chunk ends on the copy it started from).
+ * Every launch advances nsteps steps exactly as that le_step call would and
+ * writes its stress samples to the same ring rows.  Phase timing is off
+ * inside the graph.  The graph is owned by the caller (le_graph_destroy) and
+ * must not outlive the simulation.  LE_E_STATE if the simulation runs on the
+ * legacy default stream (null), which cannot be captured. */
+le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
+                          int64_t ring_cap, le_graph** out);
+
+/* Enqueue one replay on the simulation's stream.  Eager calls may be mixed
+ * with replays (e.g. le_get_state, odd le_step counts): the device control
+ * state is first moved to the copy the graph reads when needed. */
+le_status le_graph_launch(le_graph* g);
+
+le_status le_graph_destroy(le_graph* g);
 
 /* Wait for all enqueued work of the simulation; returns any latched error. */
 le_status le_sync(le_sim* s);

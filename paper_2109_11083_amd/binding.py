@@ -30,7 +30,8 @@ LE_MIXED = 1
 EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
-    "le_timing_enable", "le_timing_read", "le_observables",
+    "le_timing_enable", "le_timing_read", "le_observables", "le_graph_create", "le_graph_launch",
+    "le_graph_destroy",
 ]
 LE_MAX_BINS = 256
 
@@ -99,6 +100,9 @@ def lib() -> C.CDLL:
     L.le_timing_enable.argtypes = [vp, i32]
     L.le_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
     L.le_observables.argtypes = [vp, i32, vp]
+    L.le_graph_create.argtypes = [vp, i64, i32, vp, i64, sim_pp]
+    L.le_graph_launch.argtypes = [vp]
+    L.le_graph_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -185,6 +189,22 @@ def le_philox(ctr: int, key: int, out: int, count: int, stream: int | None) -> N
 
 def le_observables(sim: int, nbins: int, out: int) -> None:
     check(lib().le_observables(sim, nbins, out), "le_observables")
+
+
+def le_graph_create(sim: int, nsteps: int, sample_every: int = 0, stress_ring: int | None = None,
+                    ring_cap: int = 0) -> int:
+    g = C.c_void_p(0)
+    check(lib().le_graph_create(sim, nsteps, sample_every, stress_ring, ring_cap, C.byref(g)),
+          "le_graph_create")
+    return g.value
+
+
+def le_graph_launch(graph: int) -> None:
+    check(lib().le_graph_launch(graph), "le_graph_launch")
+
+
+def le_graph_destroy(graph: int) -> None:
+    check(lib().le_graph_destroy(graph), "le_graph_destroy")
 
 
 def le_timing_enable(sim: int, phases) -> None:

@@ -11,6 +11,13 @@
 
 using namespace le;
 
+struct le_graph {
+  le_sim* s;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  Ctrl* ctrl_at;   // control copy current when the graph starts
+};
+
 struct le_sim {
   le_params p;
   Dev d;
@@ -446,6 +453,62 @@ le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step
       st = LE_E_HIP;
   }
   return st;
+}
+
+le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
+                          int64_t ring_cap, le_graph** out) {
+  if (!s || !out || nsteps <= 0 || (nsteps & 1)) return LE_E_ARG;
+  if (sample_every > 0 && (!stress_ring || ring_cap <= 0)) return LE_E_ARG;
+  *out = nullptr;
+  if (!s->stream) return LE_E_STATE;  // the legacy default stream cannot be captured
+  if (s->host_status) return s->host_status;
+  le_graph* g = new (std::nothrow) le_graph();
+  if (!g) return LE_E_ARG;
+  g->s = s;
+  g->ctrl_at = s->d.ctrl;
+  const int32_t timing = s->timing;
+  s->timing = 0;
+  le_status st = hip_check(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  if (st == LE_OK) {
+    le_status st_step = le_step(s, nsteps, sample_every, stress_ring, ring_cap);
+    le_status st_end = hip_check(hipStreamEndCapture(s->stream, &g->graph));
+    st = st_step != LE_OK ? st_step : st_end;
+  }
+  s->timing = timing;
+  if (st == LE_OK && s->d.ctrl != g->ctrl_at) st = LE_E_STATE;  // cannot happen for even nsteps
+  if (st == LE_OK) st = hip_check(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  if (st != LE_OK) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return LE_OK;
+}
+
+le_status le_graph_launch(le_graph* g) {
+  if (!g) return LE_E_ARG;
+  le_sim* s = g->s;
+  if (s->host_status) return s->host_status;
+  if (s->d.ctrl != g->ctrl_at) {
+    // an odd number of control updates since the capture: move the state to
+    // the copy the graph reads (the simulation is unchanged)
+    const bool first = g->ctrl_at == s->ctrl_base;
+    unsigned long long* vat = s->vmax_base + (first ? 0 : kSlots * kLineU64);
+    le_status st = hip_check(launch_ctrl_copy(s->d.ctrl, g->ctrl_at, s->d.vmax, vat, s->stream));
+    if (st != LE_OK) return st;
+    s->d.ctrl = g->ctrl_at;
+    s->d.vmax = vat;
+  }
+  return hip_check(hipGraphLaunch(g->exec, s->stream));
+}
+
+le_status le_graph_destroy(le_graph* g) {
+  if (!g) return LE_E_ARG;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return LE_OK;
 }
 
 le_status le_sync(le_sim* s) {

@@ -142,6 +142,8 @@ hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample
                         double* sample_out, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
 hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out);
+hipError_t launch_ctrl_copy(const Ctrl* src, Ctrl* dst, const unsigned long long* vsrc,
+                            unsigned long long* vdst, hipStream_t s);
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,
                             int32_t* order);
 hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t cap,

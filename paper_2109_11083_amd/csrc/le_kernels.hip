@@ -1155,6 +1155,15 @@ __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
   reduce_partials(d, out6, virial_only != 0);
 }
 
+// Copy the current control state and speed-bound words into the other copy
+// (a no-op for the simulation; lets a captured graph start on its copy).
+__global__ void k_ctrl_copy(const Ctrl* __restrict__ src, Ctrl* __restrict__ dst,
+                            const unsigned long long* __restrict__ vsrc,
+                            unsigned long long* __restrict__ vdst) {
+  if (threadIdx.x == 0) *dst = *src;
+  for (int k = threadIdx.x; k < kSlots * kLineU64; k += blockDim.x) vdst[k] = vsrc[k];
+}
+
 // ---------------------------------------------------------- observables
 // Per block: bin of each particle (its image in the box, with the matching
 // lab u_x), then one thread per bin sums the block's particles of that bin in
@@ -1314,6 +1323,12 @@ hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
 
 // The force launches go through hipExtLaunchKernelGGL so that optional
 // events (e0, e1) take the timestamps of the dispatch itself.
+template <typename K>
+static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Dev& d,
+                     double* f_out, double* so) {
+  if (e0 || e1) hipExtLaunchKernelGGL(k, g, b, 0, s, e0, e1, 0, d, f_out, so);
+  else hipLaunchKernelGGL(k, g, b, 0, s, d, f_out, so);
+}
 template <int MODE, bool SAMPLE, bool STAGED>
 static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
                            hipEvent_t e1) {
@@ -1321,11 +1336,11 @@ static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* s
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
-    if (bonds) hipExtLaunchKernelGGL((k_force<MODE, true, true, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
-    else hipExtLaunchKernelGGL((k_force<MODE, true, false, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
+    if (bonds) launch_k(k_force<MODE, true, true, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
+    else launch_k(k_force<MODE, true, false, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
   } else {
-    if (bonds) hipExtLaunchKernelGGL((k_force<MODE, false, true, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
-    else hipExtLaunchKernelGGL((k_force<MODE, false, false, SAMPLE, STAGED>), g, b, 0, s, e0, e1, 0, d, f_out, so);
+    if (bonds) launch_k(k_force<MODE, false, true, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
+    else launch_k(k_force<MODE, false, false, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
   }
 }
 template <int MODE, bool SAMPLE>
@@ -1357,6 +1372,11 @@ hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool v
   return hipGetLastError();
 }
 
+hipError_t launch_ctrl_copy(const Ctrl* src, Ctrl* dst, const unsigned long long* vsrc,
+                            unsigned long long* vdst, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_copy, dim3(1), dim3(64), 0, s, src, dst, vsrc, vdst);
+  return hipGetLastError();
+}
 hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out) {
   const int nblk = blocks_for(d.n);
   hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kBlock), 0, s, d, nbins);

@@ -88,14 +88,16 @@ class Sim:
         self._c = params.to_c()
         self.ws_bytes = B.le_workspace_bytes(self._c)
         if workspace is None:
-            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(self.stream):
+                workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         assert workspace.numel() >= self.ws_bytes
         self.workspace = workspace
-        x0 = _dev(x0, self.device)
-        u0 = _dev(u0, self.device)
-        f0 = _dev(f0, self.device) if f0 is not None else None
-        assert x0.shape == (3, params.n) and u0.shape == (3, params.n)
         with torch.cuda.stream(self.stream):
+            # the uploads are ordered before le_init on the simulation's stream
+            x0 = _dev(x0, self.device)
+            u0 = _dev(u0, self.device)
+            f0 = _dev(f0, self.device) if f0 is not None else None
+            assert x0.shape == (3, params.n) and u0.shape == (3, params.n)
             self.handle = B.le_init(self._c, x0.data_ptr(), u0.data_ptr(),
                                     f0.data_ptr() if f0 is not None else None,
                                     workspace.data_ptr(), workspace.numel(), self.stream.cuda_stream,
@@ -145,6 +147,10 @@ class Sim:
             return ring
         B.le_step(self.handle, nsteps, 0, None, 0)
         return None
+
+    def graph(self, nsteps: int, sample_every: int = 0, ring: torch.Tensor | None = None) -> "StepGraph":
+        """Capture le_step(nsteps, sample_every, ring) as a HIP graph (nsteps even)."""
+        return StepGraph(self, nsteps, sample_every, ring)
 
     def stress(self):
         s = torch.empty(6, dtype=torch.float64, device=self.device)
@@ -198,3 +204,22 @@ def params_from_workload(w, **over) -> Params:
     kw.update(over)
     allowed = set(Params.__dataclass_fields__)
     return Params(**{k: v for k, v in kw.items() if k in allowed})
+
+
+class StepGraph:
+    """A captured chunk of steps of one simulation (le_graph_*); replay with launch()."""
+
+    def __init__(self, sim: Sim, nsteps: int, sample_every: int = 0, ring: torch.Tensor | None = None):
+        self.sim = sim
+        self.ring = ring
+        self.handle = B.le_graph_create(sim.handle, nsteps, sample_every,
+                                        ring.data_ptr() if ring is not None else None,
+                                        ring.shape[0] if ring is not None else 0)
+
+    def launch(self):
+        B.le_graph_launch(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.le_graph_destroy(self.handle)
+            self.handle = None

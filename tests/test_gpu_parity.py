@@ -408,3 +408,45 @@ def test_full_size_kg_400k_sampled():
     _log(f"kg 400k sampled e_F={err:.3e}")
     assert err <= 1e-12
     sim.close()
+
+
+def test_graph_replays_match_eager():
+    """A captured chunk of steps replayed several times, with eager work and
+    synchronisations between replays (state read-out, observables, an odd
+    eager step count), equals the same chunks run eagerly, bit for bit."""
+    w, p = _lj_case(shear_rate=0.4, skin=0.3)
+    a = Sim(p, w.x, w.u)
+    sb = torch.cuda.Stream()
+    b = Sim(p, w.x, w.u, stream=sb)
+    ring_a = torch.zeros((5, 6), dtype=torch.float64, device=DEV)
+    with torch.cuda.stream(sb):
+        ring_b = torch.zeros((5, 6), dtype=torch.float64, device=DEV)
+    sb.synchronize()
+    g = b.graph(50, sample_every=10, ring=ring_b)
+    for rep in range(4):
+        a.step(50, sample_every=10, ring=ring_a)
+        g.launch()
+        b.sync()
+        xa, ua, fa, sta = a.state()
+        xb, ub, fb, stb = b.state()
+        assert sta == stb
+        assert np.array_equal(xa, xb) and np.array_equal(ua, ub) and np.array_equal(fa, fb), rep
+        torch.cuda.synchronize()
+        assert torch.equal(ring_a, ring_b), rep
+        oa, ob = a.observables(10), b.observables(10)
+        assert np.array_equal(oa["sum_ux"], ob["sum_ux"])
+        if rep == 1:  # an odd eager count in both
+            a.step(3)
+            b.step(3)
+    g.close()
+    a.close()
+    b.close()
+
+
+def test_graph_on_default_stream_is_refused():
+    w, p = _lj_case()
+    sim = Sim(p, w.x, w.u)  # torch's default stream
+    with pytest.raises(B.LeError) as e:
+        sim.graph(10)
+    assert e.value.code == B.LE_E_STATE
+    sim.close()
