@@ -100,7 +100,8 @@ typedef struct le_params {
   int32_t pair;        /* LE_PAIR_LJ or LE_PAIR_WCA                                 */
   int32_t precision;   /* LE_FP64 or LE_MIXED                                       */
   int32_t cells[3];    /* cell grid; 0 = floor(L_a / (rc + skin)); each must be >= 3 */
-  int32_t max_neighbors; /* neighbour-list capacity per particle; 0 = from density  */
+  int32_t max_neighbors; /* neighbour-list capacity per particle (two sub-lists of half
+                            each); 0 = from density */
   int32_t tune;        /* pair-kernel layout: 0 = chosen from density, 1 = partners staged
                           in an LDS halo per tile, 2 = partners read from global memory;
                           the physics is the same (sums may differ in the last bits) */

@@ -81,12 +81,14 @@ le_status validate(const le_params* p, Geometry* g) {
   if ((int64_t)g->nc[0] * g->nc[1] * g->nc[2] > (int64_t)0x7fffffff - 1) return LE_E_GEOMETRY;
   g->rc = rc;
   g->rlist = rlist;
+  // capacity of each of a particle's two sub-lists (each holds about half of
+  // its partners): max_neighbors / 2, or from the density with a margin
   if (p->max_neighbors > 0) {
-    g->K = p->max_neighbors;
+    g->K = (p->max_neighbors + 1) / 2;
   } else {
     double rho = (double)p->n / (p->box[0] * p->box[1] * p->box[2]);
     double mean = 4.0 / 3.0 * M_PI * rlist * rlist * rlist * rho;
-    g->K = (int32_t)ceil(2.0 * mean) + 32;
+    g->K = (int32_t)ceil(mean) + 40;
   }
   if (g->K > 4096) g->K = 4096;
   g->K = (g->K + 7) / 8 * 8;  // lists are stored in blocks of 8 (plain) and 4 (other) entries
@@ -129,11 +131,11 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.bucket = (int32_t*)take(ncell * (size_t)g.bcap * sizeof(int32_t));
   t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
-  t.nl16 = (uint16_t*)take((size_t)g.K * np * sizeof(uint16_t));
-  t.nlo = (uint32_t*)take((size_t)g.K * np * sizeof(uint32_t));
-  t.nlc = (uint8_t*)take((size_t)g.K * np);
-  t.n_plain = (int32_t*)take(np * sizeof(int32_t));
-  t.n_og = (int32_t*)take(np * sizeof(int32_t));
+  t.nl16 = (uint16_t*)take((size_t)g.K * 2 * np * sizeof(uint16_t));
+  t.nlo = (uint32_t*)take((size_t)g.K * 2 * np * sizeof(uint32_t));
+  t.nlc = (uint8_t*)take((size_t)g.K * 2 * np);
+  t.n_plain = (int32_t*)take(2 * np * sizeof(int32_t));
+  t.n_og = (int32_t*)take(2 * np * sizeof(int32_t));
   t.halo_slot = (int32_t*)take((size_t)g.nblocks * kHalo * sizeof(int32_t));
   t.halo_code = (uint8_t*)take((size_t)g.nblocks * kHalo);
   t.tile_nstage = (int32_t*)take((size_t)g.nblocks * sizeof(int32_t));
@@ -209,6 +211,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->n = (int32_t)p->n;
   d->np = (int32_t)g.np;
   d->K = g.K;
+  d->np2 = (int32_t)(2 * g.np);
   d->chain_len = p->n_chains > 0 ? p->chain_len : 0;
   d->n_bonded = (int32_t)(p->n_chains * (int64_t)p->chain_len);
   d->precision = p->precision;

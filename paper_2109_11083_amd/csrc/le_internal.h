@@ -67,7 +67,8 @@ struct Dev {
   double inv_vol;
   int32_t nx, ny, nz, ncell;
   int32_t n, np;                   // particles, padded stride (np > n: slot n is a far-away sentinel)
-  int32_t K;                       // neighbour capacity per particle
+  int32_t K;                       // capacity of each of a particle's two sub-lists
+  int32_t np2;                     // 2 * np: sub-list v = h * np + i of particle i, h = 0, 1
   int32_t chain_len;
   int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
   int32_t precision;
@@ -90,19 +91,20 @@ struct Dev {
   int32_t* bucket;                 // [ncell][bcap] slots binned into each cell (arrival order)
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
-  // Neighbour lists.  Entry k of particle i lives in a block of consecutive
-  // entries of that particle: blocks of 8 (one 16-byte load) for nl16, of 4
-  // for nlo/nlc; block b of particles i, i+1, ... is contiguous.
+  // Neighbour lists: two sub-lists per particle (v = h * np + i, h = 0, 1,
+  // the two halves of each stencil range).  Entry k of sub-list v lives in a
+  // block of consecutive entries: blocks of 8 (one 16-byte load) for nl16, of
+  // 4 for nlo/nlc; block b of sub-lists v, v+1, ... is contiguous.
   //   nl16  partners staged in the tile's LDS halo (any image): LDS index,
-  //         element k at ((k/8)*np + i)*8 + k%8
+  //         element k at ((k/8)*np2 + v)*8 + k%8
   //   nlo   partners not staged: slot in global memory, element k at
-  //         ((k/4)*np + i)*4 + k%4
+  //         ((k/4)*np2 + v)*4 + k%4
   //   nlc   image code of each nlo entry, same layout (bytes)
   uint16_t* nl16;
   uint32_t* nlo;
   uint8_t* nlc;
-  int32_t* n_plain;                // [np] staged entries, multiple of kPlainBatch
-  int32_t* n_og;                   // [np] global entries, multiple of kOtherBatch
+  int32_t* n_plain;                // [np2] staged entries per sub-list, multiple of kPlainBatch
+  int32_t* n_og;                   // [np2] global entries per sub-list, multiple of kOtherBatch
   int32_t* halo_slot;              // [ntiles][kHalo] slot staged at each LDS position
   uint8_t* halo_code;              // [ntiles][kHalo] image code of each staged position
   int32_t* tile_nstage;            // [ntiles] staged positions per tile

@@ -447,23 +447,30 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
   return r2 < d.rlist2;
 }
 
-__global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
+// Two threads per particle: thread t (half 0) and t + kTile (half 1) split
+// each (dy, dz) range in two and write two sub-lists, which the force kernel
+// consumes with two threads per particle in the same way.
+__global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[kHalo + 8], hy[kHalo + 8], hz[kHalo + 8];
   __shared__ Pieces pc;
-  // per-lane ring of list entries, and a spare entry for rejected ones
-  __shared__ __align__(16) uint16_t lbuf[kTile][16];
-  __shared__ uint16_t lspare[kTile];
+  // per-thread ring of list entries, and a spare entry for rejected ones
+  __shared__ __align__(16) uint16_t lbuf[2 * kTile][16];
+  __shared__ uint16_t lspare[2 * kTile];
+  __shared__ int cnt1[kTile];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
   __syncthreads();
   if (skip) return;
-  const int np = d.np, K = d.K, n = d.n;
+  const int np = d.np, np2 = d.np2, K = d.K, n = d.n;
   const int tile = xcd_block(d.ntiles);
   const int s0 = tile * kTile;
-  const int i = s0 + threadIdx.x;
+  const int half = (int)(threadIdx.x / kTile);
+  const int tl = (int)threadIdx.x - half * kTile;
+  const int i = s0 + tl;
+  const int v = half * np + i;  // this thread's sub-list
   const bool valid = i < n;
   const int pn = c->pos_cur, an = c->aux_cur;  // sorted buffers of the new state
   const double4* P = reinterpret_cast<const double4*>(d.pos[pn]);
@@ -484,7 +491,7 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
   __syncthreads();
   // ---- pieces: one thread per (covered row, dz, dy)
   const int ncombo = tg.staged_ok ? tg.nrows * 9 : 0;
-  for (int t = threadIdx.x; t < ncombo; t += kTile) {
+  for (int t = threadIdx.x; t < ncombo; t += blockDim.x) {
     int r = t / 9, rem = t % 9;
     int dzc = rem / 3 - 1, dyc = rem % 3 - 1;
     int row = tg.row_first + r;
@@ -519,37 +526,39 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
   // ---- LDS offsets in a fixed order (prefix sum over the pieces); pieces that
   // do not fit stay global
   {
+    // (the first kTile threads, two rounds; the others only meet the barriers)
     __shared__ int wsum[kWaves];
     const int npieces = ncombo * kPieces;  // <= kMaxRows * 9 * kPieces <= 2 * kTile
+    const bool pt = threadIdx.x < kTile;
     int cnt[2], incl[2];
     int tot_prev = 0;
-    for (int half = 0; half < 2; ++half) {
-      int e = half * kTile + threadIdx.x;
+    for (int rd = 0; rd < 2; ++rd) {
+      int e = rd * kTile + (int)threadIdx.x;
       int t = e / kPieces, q = e % kPieces;
-      cnt[half] = (e < npieces && q < pc.npc[t]) ? pc.count[t][q] : 0;
-      // block inclusive scan of cnt[half]
+      cnt[rd] = (pt && e < npieces && q < pc.npc[t]) ? pc.count[t][q] : 0;
+      // block inclusive scan of cnt[rd] over the first kTile threads
       int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      int v = cnt[half];
+      int val = cnt[rd];
       for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
+        int u = __shfl_up(val, o, 64);
+        if (lane >= o) val += u;
       }
-      if (lane == 63) wsum[wv] = v;
+      if (lane == 63 && wv < kWaves) wsum[wv] = val;
       __syncthreads();
       int woff = 0, wtot = 0;
       for (int w2 = 0; w2 < kWaves; ++w2) { if (w2 < wv) woff += wsum[w2]; wtot += wsum[w2]; }
-      incl[half] = tot_prev + woff + v;
+      incl[rd] = tot_prev + woff + val;
       tot_prev += wtot;
       __syncthreads();
     }
     // a piece is staged iff it ends within the halo; the staged set is a prefix
-    for (int half = 0; half < 2; ++half) {
-      int e = half * kTile + threadIdx.x;
-      if (e < npieces) {
+    for (int rd = 0; rd < 2; ++rd) {
+      int e = rd * kTile + (int)threadIdx.x;
+      if (pt && e < npieces) {
         int t = e / kPieces, q = e % kPieces;
         bool real = q < pc.npc[t];
-        int start_off = incl[half] - cnt[half];
-        pc.off[t][q] = (real && incl[half] <= kHalo) ? start_off : -1;
+        int start_off = incl[rd] - cnt[rd];
+        pc.off[t][q] = (real && incl[rd] <= kHalo) ? start_off : -1;
       }
     }
     __syncthreads();
@@ -577,11 +586,11 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
   const double4 org = P[s0];
   {
     const int tot = pc.ntot, nseg = pc.nseg;
-    for (int h0 = threadIdx.x; h0 < tot; h0 += 4 * kTile) {
+    for (int h0 = threadIdx.x; h0 < tot; h0 += 4 * blockDim.x) {
       int slot[4], code[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        int h = h0 + u * kTile;
+        int h = h0 + u * blockDim.x;
         slot[u] = n;
         code[u] = 0;
         if (h < tot) {
@@ -599,7 +608,7 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
       for (int u = 0; u < 4; ++u) pj[u] = P[slot[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        int h = h0 + u * kTile;
+        int h = h0 + u * blockDim.x;
         if (h < tot) {
           int sx, sy, sz;
           unpack_img((uint8_t)code[u], sx, sy, sz);
@@ -656,6 +665,9 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
       if (qa >= 0 && qb < pc.npc[t] && pc.off[t][qb] >= 0) {
         a = d.cell_start[rowbase + (klo - sxa * d.nx)] + (pc.off[t][qa] - pc.start[t][qa]);
         b = d.cell_start[rowbase + (khi - sxb * d.nx) + 1] + (pc.off[t][qb] - pc.start[t][qb]);
+        // the two threads of the particle take the two halves of the range
+        const int mid = a + (b - a + 1) / 2;
+        if (half == 0) b = mid; else a = mid;
         walk_global = false;
       }
     }
@@ -698,8 +710,8 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
           const int u = __builtin_ctz(m_in);
           m_in &= m_in - 1u;
           if (nog < K) {
-            d.nlo[idx4(nog, i, np)] = (uint32_t)d.halo_slot[hbase + h0 + u];
-            d.nlc[idx4(nog, i, np)] = d.halo_code[hbase + h0 + u];
+            d.nlo[idx4(nog, v, np2)] = (uint32_t)d.halo_slot[hbase + h0 + u];
+            d.nlc[idx4(nog, v, np2)] = d.halo_code[hbase + h0 + u];
           }
           ++nog;
         }
@@ -718,14 +730,17 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
       if ((nn >> 3) != (npl >> 3)) {
         const int blk = npl >> 3;
         if ((blk + 1) * 8 <= K)
-          reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np + i] =
+          reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
               *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
       }
       npl = nn;
     }
     if (walk_global) {
-      // this particle's cells of the row, read from global memory
-      for (int k = klo; k <= khi; ++k) {
+      // this particle's cells of the row, read from global memory; the two
+      // threads of the particle take the lower and the upper cells
+      const int kmid = klo + (khi - klo) / 2;
+      const int ka = half == 0 ? klo : kmid + 1, kb = half == 0 ? kmid : khi;
+      for (int k = ka; k <= kb; ++k) {
         const int sx = floor_div(k, d.nx);
         const int cell = rowbase + (k - sx * d.nx);
         const bool plain = (sx == 0 && sy == 0 && sz == 0);
@@ -734,21 +749,23 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
           if (plain && q == i) continue;
           if (in_list_exact(d, pi, P[q], (double)sx * d.Lx, (double)sy * d.Ly, (double)sz * d.Lz,
                             (double)sy * Delta)) {
-            if (nog < K) { d.nlo[idx4(nog, i, np)] = (uint32_t)q; d.nlc[idx4(nog, i, np)] = code; }
+            if (nog < K) { d.nlo[idx4(nog, v, np2)] = (uint32_t)q; d.nlc[idx4(nog, v, np2)] = code; }
             ++nog;
           }
         }
       }
     }
   }
-  {  // telemetry: one atomic per block, spread over kSlots words
-    __shared__ int wmax[kTile / 64];
-    int mx = npl + nog;
+  {  // telemetry (entries per particle, both sub-lists): one atomic per block
+    __shared__ int wmax[2 * kTile / 64];
+    if (half == 1) cnt1[tl] = npl + nog;
+    __syncthreads();
+    int mx = half == 0 ? npl + nog + cnt1[tl] : 0;
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int w = 1; w < kTile / 64; ++w) mx = max(mx, wmax[w]);
+      for (int w = 1; w < 2 * kTile / 64; ++w) mx = max(mx, wmax[w]);
       atomicMax(&d.flags->max_nb_slot[(blockIdx.x % kSlots) * kLineInts], mx);
     }
   }
@@ -762,15 +779,15 @@ __global__ void __launch_bounds__(kTile) k_neighbors(Dev d) {
     if (npl < npl_p) {  // pad and flush the partial block
       const int blk = npl >> 3;
       for (int r = npl; r < npl_p; ++r) lbuf[threadIdx.x][r & 15] = (uint16_t)kHalo;
-      reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np + i] =
+      reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
           *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
     }
     const uint8_t zero = pack_img(0, 0, 0);
-    for (int r = nog; r < nog_p; ++r) { d.nlo[idx4(r, i, np)] = (uint32_t)n; d.nlc[idx4(r, i, np)] = zero; }
+    for (int r = nog; r < nog_p; ++r) { d.nlo[idx4(r, v, np2)] = (uint32_t)n; d.nlc[idx4(r, v, np2)] = zero; }
   }
-  d.n_plain[i] = npl_p;
-  d.n_og[i] = nog_p;
-  if (d.chain_len > 0) {
+  d.n_plain[v] = npl_p;
+  d.n_og[v] = nog_p;
+  if (d.chain_len > 0 && half == 0) {
     int tg_ = d.tag[an][i];
     int lo = -1, hi = -1;
     if (tg_ < d.n_bonded) {
@@ -927,11 +944,17 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 //   kStepFused   as kStepLast, then the next half-kick and drift
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
+// With the LDS halo the block has two threads per particle: thread t and
+// t + kTile take alternate batches of the particle's list (twice the waves
+// per CU for the same LDS), and the second hands its partial sums to the
+// first through LDS before the epilogue.
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED>
-__global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_out,
-                                                 double* __restrict__ sample_out) {
+__global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__ f_out,
+                                                     double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
   constexpr int kH = STAGED ? kHalo + 1 : 1;  // no halo: every partner from global memory
+  constexpr int kTh = STAGED ? 2 * kTile : kTile;  // threads per block
+  static_assert(!STAGED || kHalo + 1 >= kTile * 9, "the halo array holds the partial-sum exchange");
   __shared__ double hx[kH], hy[kH], hz[kH];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
@@ -939,7 +962,9 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
   __syncthreads();
   if (skip) return;
   const int lb = xcd_block(d.ntiles);
-  const int i = lb * kTile + threadIdx.x;
+  const int half = STAGED ? (int)(threadIdx.x / kTile) : 0;
+  const int tl = (int)threadIdx.x - half * kTile;  // particle within the tile
+  const int i = lb * kTile + tl;
   const bool valid = i < d.n;
   const int np = d.np;
   const int pc = c->pos_cur, ac = c->aux_cur;
@@ -955,14 +980,14 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
     const int nst = d.tile_nstage[lb];
     const int* hs = d.halo_slot + (size_t)lb * kHalo;
     const uint8_t* hc = d.halo_code + (size_t)lb * kHalo;
-    constexpr int U = kHalo / kTile;
+    constexpr int U = kHalo / kTh;
     int slot[U];
     uint8_t code[U];
     const int nsent = d.n;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       // always load from an index inside this tile's table, then select the value
-      int h = threadIdx.x + u * kTile;
+      int h = threadIdx.x + u * kTh;
       int hh = h < nst ? h : 0;
       int sv = hs[hh];
       uint8_t cv = hc[hh];
@@ -971,7 +996,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int h = threadIdx.x + u * kTile;
+      int h = threadIdx.x + u * kTh;
       double4 pj = P[slot[u]];
       int sx, sy, sz;
       unpack_img(code[u], sx, sy, sz);
@@ -991,22 +1016,32 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
   if (valid) {
     pi = P[i];
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
-    // staged partners (already shifted to their image): one 16-byte index load
-    // per batch of 8, two batches ahead
-    const int nb = STAGED ? d.n_plain[i] / kPlainBatch : 0;
+    // staged partners (already shifted to their image): the particle's two
+    // sub-lists read as one sequence of batches of 8, of which this thread
+    // takes batches half, half + 2, ...; one 16-byte index load per batch,
+    // two of this thread's batches ahead.  Loads always read an existing block
+    // of the list array and the value is selected afterwards (a select between
+    // pointers would become a flat load).
+    const int np2 = d.np2;
+    const int nb0 = STAGED ? d.n_plain[i] / kPlainBatch : 0;
+    const int nb = STAGED ? nb0 + d.n_plain[np + i] / kPlainBatch : 0;
     const uint4* __restrict__ l8 = reinterpret_cast<const uint4*>(d.nl16) + i;
     const uint4 zero4 = make_uint4(kHalo | (kHalo << 16), kHalo | (kHalo << 16), kHalo | (kHalo << 16),
                                    kHalo | (kHalo << 16));
-    // loads always read an existing block of the list array and the value is
-    // selected afterwards (a select between pointers would become a flat load)
     const int last_blk = d.K / kPlainBatch - 1;
-    uint4 t0 = l8[0];
-    uint4 t1 = l8[(size_t)min(1, last_blk) * np];
-    uint4 v0 = nb > 0 ? t0 : zero4;
-    uint4 v1 = nb > 1 ? t1 : zero4;
-    for (int b = 0; b < nb; ++b) {
-      uint4 t2 = l8[(size_t)min(b + 2, last_blk) * np];
-      uint4 v2 = (b + 2 < nb) ? t2 : zero4;
+    // offset (in uint4) of batch b of the sequence from l8
+    auto boff = [&](int b) -> size_t {
+      const int sub = b < nb0 ? 0 : 1;
+      const int blk = min(b - sub * nb0, last_blk);
+      return (size_t)blk * np2 + (size_t)sub * np;
+    };
+    uint4 t0 = l8[boff(half)];
+    uint4 t1 = l8[boff(half + 2)];
+    uint4 v0 = nb > half ? t0 : zero4;
+    uint4 v1 = nb > half + 2 ? t1 : zero4;
+    for (int b = half; b < nb; b += 2) {
+      uint4 t2 = l8[boff(b + 4)];
+      uint4 v2 = (b + 4 < nb) ? t2 : zero4;
       int j[8] = {(int)(v0.x & 0xffff), (int)(v0.x >> 16), (int)(v0.y & 0xffff), (int)(v0.y >> 16),
                   (int)(v0.z & 0xffff), (int)(v0.z >> 16), (int)(v0.w & 0xffff), (int)(v0.w >> 16)};
       double xj[8], yj[8], zj[8];
@@ -1023,20 +1058,24 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       v1 = v2;
     }
     // partners that were not staged: global memory, exact image arithmetic;
-    // eight gathers in flight, the next eight indices requested ahead
-    const int nbo = d.n_og[i] / kOtherBatch;
+    // eight gathers in flight, the next eight indices requested ahead.  With
+    // the halo each thread takes its own sub-list; without, one thread per
+    // particle takes both.
+    for (int sub = STAGED ? half : 0; sub < (STAGED ? half + 1 : 2); ++sub) {
+    const int vo = sub * np + i;
+    const int nbo = d.n_og[vo] / kOtherBatch;
     const int last_ob = d.K / kOtherBatch - 1;
-    const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo) + i;
-    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc) + i;
-    uint4 jn0 = l4[0], jn1 = l4[(size_t)min(1, last_ob) * np];
-    uint32_t cn0 = c4[0], cn1 = c4[(size_t)min(1, last_ob) * np];
+    const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo) + vo;
+    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc) + vo;
+    uint4 jn0 = l4[0], jn1 = l4[(size_t)min(1, last_ob) * np2];
+    uint32_t cn0 = c4[0], cn1 = c4[(size_t)min(1, last_ob) * np2];
     for (int b = 0; b < nbo; b += 2) {
       const uint4 j0 = jn0, j1 = jn1;
       const uint32_t c0 = cn0, c1 = cn1;
-      jn0 = l4[(size_t)min(b + 2, last_ob) * np];
-      jn1 = l4[(size_t)min(b + 3, last_ob) * np];
-      cn0 = c4[(size_t)min(b + 2, last_ob) * np];
-      cn1 = c4[(size_t)min(b + 3, last_ob) * np];
+      jn0 = l4[(size_t)min(b + 2, last_ob) * np2];
+      jn1 = l4[(size_t)min(b + 3, last_ob) * np2];
+      cn0 = c4[(size_t)min(b + 2, last_ob) * np2];
+      cn1 = c4[(size_t)min(b + 3, last_ob) * np2];
       const bool second = b + 1 < nbo;  // entries of the second block are the list's
       const uint32_t sl[8] = {j0.x, j0.y, j0.z, j0.w, second ? j1.x : (uint32_t)d.n,
                               second ? j1.y : (uint32_t)d.n, second ? j1.z : (uint32_t)d.n,
@@ -1057,7 +1096,8 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
         add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
       }
     }
-    if (BONDS) {
+    }
+    if (BONDS && half == 0) {
       // FENE (Eq. fene), always float64; displacement by the nearest image
       for (int b = 0; b < 2; ++b) {
         int j = d.bond[b * np + i];
@@ -1083,10 +1123,28 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       }
     }
   }
+  if (STAGED) {
+    // the second thread of each particle hands over its partial sums (the
+    // halo array is free once every thread has left the pair loops)
+    __syncthreads();
+    double* ex = hx + tl * 9;
+    if (half == 1) {
+      ex[0] = fx; ex[1] = fy; ex[2] = fz;
+      if (VIR) for (int q = 0; q < 6; ++q) ex[3 + q] = w[q];
+    }
+    __syncthreads();
+    if (half == 0) {
+      fx += ex[0]; fy += ex[1]; fz += ex[2];
+      if (VIR) for (int q = 0; q < 6; ++q) w[q] += ex[3 + q];
+    } else {
+      for (int q = 0; q < 6; ++q) w[q] = 0.0;
+    }
+  }
+  const bool ep = valid && half == 0;  // threads that finish a particle
   double kin[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double v2 = 0.0;
   if (MODE == kForcesOnly) {
-    if (valid) {
+    if (ep) {
       int t = d.tag[ac][i];
       if (f_out) {
         f_out[t] = fx; f_out[d.n + t] = fy; f_out[2 * d.n + t] = fz;
@@ -1098,7 +1156,7 @@ __global__ void __launch_bounds__(kTile) k_force(Dev d, double* __restrict__ f_o
       kin[0] = m * cx * cx; kin[1] = m * cy * cy; kin[2] = m * cz * cz;
       kin[3] = m * cx * cy; kin[4] = m * cx * cz; kin[5] = m * cy * cz;
     }
-  } else if (valid) {
+  } else if (ep) {
     double* U = d.vel[ac];
     double ux = U[i], uy = U[np + i], uz = U[2 * np + i];
     int t = d.tag[ac][i];
@@ -1260,15 +1318,18 @@ __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long lo
   const int32_t* tag = d.tag[d.ctrl->aux_cur];
   const int* hs = d.halo_slot + (size_t)(i / kTile) * kHalo;
   const int ti = tag[i];
-  const int npl = d.n_plain[i], nog = d.n_og[i];
+  const int np2 = d.np2;
+  for (int sub = 0; sub < 2; ++sub) {
+  const int v = sub * np + i;
+  const int npl = d.n_plain[v], nog = d.n_og[v];
   for (int k = 0; k < npl + nog; ++k) {
     int slot;
     if (k < npl) {
-      int h = d.nl16[idx8(k, i, np)];
+      int h = d.nl16[idx8(k, v, np2)];
       if (h == kHalo) continue;
       slot = hs[h];
     } else {
-      slot = (int)d.nlo[idx4(k - npl, i, np)];
+      slot = (int)d.nlo[idx4(k - npl, v, np2)];
       if (slot == d.n) continue;
     }
     int tj = tag[slot];
@@ -1276,6 +1337,7 @@ __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long lo
       unsigned long long idx = atomicAdd(counter, 1ull);
       if ((int64_t)idx < cap) { pairs[2 * idx] = ti; pairs[2 * idx + 1] = tj; }
     }
+  }
   }
 }
 
@@ -1313,7 +1375,7 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
                      force ? 1 : 0, control ? 1 : 0);
   hipLaunchKernelGGL(k_cell_scan, dim3((d.ncell + kScanTile - 1) / kScanTile), dim3(kScanBlock), 0, s, dn);
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
-  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(kTile), 0, s, dn);
+  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
   return hipGetLastError();
 }
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
@@ -1332,7 +1394,7 @@ static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent
 template <int MODE, bool SAMPLE, bool STAGED>
 static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
                            hipEvent_t e1) {
-  dim3 g(d.ntiles), b(kTile);
+  dim3 g(d.ntiles), b(STAGED ? 2 * kTile : kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
