@@ -35,6 +35,7 @@ PEAK_HBM_GBS = 8000.0
 PAIR_FLOPS = 26.0             # per in-cutoff pair, counted once per unordered pair
 STEP_FLOPS = 40.0             # thermostat + velocity Verlet per particle
 BYTES_FUSED = 100.0           # fused step, per particle: read x, u, tag; write x, u
+TIMING_FORCE = 0x1 | (8 << 8)  # event-time every 8th plain-step force launch (phase 0)
 
 
 def log(msg):
@@ -76,10 +77,10 @@ def pick_skin(n, shear_rate, precision, workload):
     return best.skin, [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
 
 
-def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=0x1, skin=0.3,
+def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIMING_FORCE, skin=0.3,
             workload="lj"):
-    """One timed run.  timing: phase mask for HIP-event timing inside the timed
-    region (bit 0: the plain-step force kernel; 0xF: every phase)."""
+    """One timed run.  timing: le_timing_enable mask for HIP-event timing inside the
+    timed region (bit 0: the plain-step force kernel; 0xF: every phase; bits 8..: stride)."""
     import torch
     from paper_2109_11083_amd import binding as B
     from paper_2109_11083_amd.sim import Sim
@@ -248,12 +249,13 @@ def main():
     log(f"bench: {args.workload} {size} shear_rate={sr} {args.precision} "
         f"steps={args.steps} warmup={args.warmup} skin={skin}")
     r = run_gpu(args.n, sr, args.precision, args.steps, args.warmup,
-                timing=0 if args.no_timing else 0x1, skin=args.skin, workload=args.workload)
+                timing=0 if args.no_timing else TIMING_FORCE, skin=args.skin, workload=args.workload)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
 
     # roofline of the dominant kernel: the fused force / thermostat / integrator
-    # kernel of plain steps (timing phase 0), from its event-timed average
+    # kernel of plain steps (timing phase 0), from its event-timed average over
+    # every 8th launch of the timed region
     force_ms, force_n = r["phases"]["force"]
     roofline = None
     kname = ("k_force_kg400k_" if kg else "k_force_lj256k_") + args.precision

@@ -211,8 +211,10 @@ le_status le_stats(le_sim* s, int64_t* rebuilds, int32_t* max_neighbors);
  * without a rebuild), 2 the first half-kick of a call, 3 sampled steps (the
  * force kernel with the virial, then the stress reduction).  enabled is a bit
  * mask over the phases (bit k: phase k; 0 switches timing off, 0xF times
- * all); enabling resets the totals.  Creating events is the only host-side
- * resource it takes. */
+ * all); bits 8..23 hold a stride s (0 means 1): only every s-th plain-step
+ * force launch is timed, so the events barely perturb the run.  Enabling
+ * resets the totals.  Creating events is the only host-side resource it
+ * takes. */
 le_status le_timing_enable(le_sim* s, int32_t enabled);
 
 /* Totals since the last enable (waits for the stream): ms[4] elapsed device

@@ -29,6 +29,8 @@ struct le_sim {
   double* scratch6;                    // device 6 doubles
   // phase timing (le_timing_enable)
   int32_t timing;                      // bit k: time phase k
+  int32_t timing_stride;               // time every timing_stride-th plain-step force launch
+  uint64_t tick;                       // plain-step force launches since enabling
   std::vector<hipEvent_t> ev;          // pairs (start, stop)
   std::vector<int> ev_phase;           // phase of each recorded pair
   size_t ev_used;                      // pairs recorded and not yet folded
@@ -328,6 +330,8 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   if (!s) return LE_E_ARG;
   s->host_status = 0;
   s->timing = 0;
+  s->timing_stride = 1;
+  s->tick = 0;
   s->ev_used = 0;
   for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
   s->p = *p;
@@ -417,7 +421,7 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
       }
       end_phase(s, ev);
     } else {
-      ev = reserve_pair(s, 0);
+      ev = (s->tick++ % s->timing_stride == 0) ? reserve_pair(s, 0) : -1;
       st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, false, nullptr, nullptr,
                                   ev >= 0 ? s->ev[2 * ev] : nullptr,
                                   ev >= 0 ? s->ev[2 * ev + 1] : nullptr));
@@ -539,6 +543,9 @@ le_status le_timing_enable(le_sim* s, int32_t enabled) {
   if (!s) return LE_E_ARG;
   le_status st = fold_events(s);
   s->timing = enabled & 0xF;
+  const int32_t stride = (enabled >> 8) & 0xFFFF;
+  s->timing_stride = stride > 0 ? stride : 1;
+  s->tick = 0;
   for (int k = 0; k < 4; ++k) { s->phase_ms[k] = 0.0; s->phase_n[k] = 0; }
   return st;
 }

@@ -608,13 +608,16 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
       for (int u = 0; u < 4; ++u) pj[u] = P[slot[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        int h = h0 + u * blockDim.x;
+        const int h = h0 + u * blockDim.x;
+        // written unconditionally (past the halo: a spare entry) so that the
+        // loads above are not sunk into the condition one by one
+        const int hw = h < tot ? h : kHalo + 7;
+        int sx, sy, sz;
+        unpack_img((uint8_t)code[u], sx, sy, sz);
+        hx[hw] = (float)((pj[u].x + ((double)sy * Delta + (double)sx * d.Lx)) - org.x);
+        hy[hw] = (float)((pj[u].y + (double)sy * d.Ly) - org.y);
+        hz[hw] = (float)((pj[u].z + (double)sz * d.Lz) - org.z);
         if (h < tot) {
-          int sx, sy, sz;
-          unpack_img((uint8_t)code[u], sx, sy, sz);
-          hx[h] = (float)((pj[u].x + ((double)sy * Delta + (double)sx * d.Lx)) - org.x);
-          hy[h] = (float)((pj[u].y + (double)sy * d.Ly) - org.y);
-          hz[h] = (float)((pj[u].z + (double)sz * d.Lz) - org.z);
           d.halo_slot[(size_t)tile * kHalo + h] = slot[u];
           d.halo_code[(size_t)tile * kHalo + h] = (uint8_t)code[u];
         }
@@ -971,6 +974,27 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
   const double Delta = c->Delta;
   const int W = c->wraps;
   const double4* P = reinterpret_cast<const double4*>(d.pos[pc]);
+  // Per-particle data and the first list blocks are requested before and
+  // during the halo staging so that their latency overlaps it (loads use a
+  // clamped index; values of invalid lanes are never used).
+  const int ic = valid ? i : 0;
+  const int np2 = d.np2;
+  const double4 pi_ld = P[ic];
+  const int npl0_ld = d.n_plain[ic], npl1_ld = d.n_plain[np + ic];
+  const double* Uv = d.vel[ac];
+  const double u0_ld = Uv[ic], u1_ld = Uv[np + ic], u2_ld = Uv[2 * np + ic];
+  const int tag_ld = d.tag[ac][ic];
+  const uint4* __restrict__ l8 = reinterpret_cast<const uint4*>(d.nl16) + ic;
+  const int last_blk = d.K / kPlainBatch - 1;
+  const int nb0 = STAGED ? npl0_ld / kPlainBatch : 0;
+  // offset (in uint4) of batch b of the particle's two sub-lists read as one
+  // sequence (sub-list 0, then sub-list 1)
+  auto boff = [&](int b) -> size_t {
+    const int sub = b < nb0 ? 0 : 1;
+    const int blk = min(b - sub * nb0, last_blk);
+    return (size_t)blk * np2 + (size_t)sub * np;
+  };
+  uint4 t0 = make_uint4(0u, 0u, 0u, 0u), t1 = t0;
   // Stage the tile's halo: the slots recorded at the last build with their
   // current positions, each shifted by its periodic / Lees-Edwards image
   // (sy Delta + sx L_x, sy L_y, sz L_z; the x image absorbs the offset's
@@ -994,27 +1018,31 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       slot[u] = (h < nst) ? sv : nsent;
       code[u] = (h < nst) ? cv : pack_img(0, 0, 0);
     }
+    t0 = l8[boff(half)];
+    t1 = l8[boff(half + 2)];
+    // every position is loaded and written (past nst: the sentinel slot, an
+    // unused LDS entry), so that no load is sunk into a condition and all of
+    // them are in flight together
+    double4 pj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pj[u] = P[slot[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int h = threadIdx.x + u * kTh;
-      double4 pj = P[slot[u]];
+      const int h = threadIdx.x + u * kTh;
       int sx, sy, sz;
       unpack_img(code[u], sx, sy, sz);
       sx += sy * W;
-      if (h < nst) {
-        hx[h] = pj.x + ((double)sy * Delta + (double)sx * d.Lx);
-        hy[h] = pj.y + (double)sy * d.Ly;
-        hz[h] = pj.z + (double)sz * d.Lz;
-      }
+      hx[h] = pj[u].x + ((double)sy * Delta + (double)sx * d.Lx);
+      hy[h] = pj[u].y + (double)sy * d.Ly;
+      hz[h] = pj[u].z + (double)sz * d.Lz;
     }
     if (threadIdx.x == 0) { hx[kHalo] = 1e100; hy[kHalo] = 1e100; hz[kHalo] = 1e100; }
     __syncthreads();
   }
   double fx = 0.0, fy = 0.0, fz = 0.0;
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+  const double4 pi = valid ? pi_ld : make_double4(0.0, 0.0, 0.0, 0.0);
   if (valid) {
-    pi = P[i];
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
     // staged partners (already shifted to their image): the particle's two
     // sub-lists read as one sequence of batches of 8, of which this thread
@@ -1022,21 +1050,9 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     // two of this thread's batches ahead.  Loads always read an existing block
     // of the list array and the value is selected afterwards (a select between
     // pointers would become a flat load).
-    const int np2 = d.np2;
-    const int nb0 = STAGED ? d.n_plain[i] / kPlainBatch : 0;
-    const int nb = STAGED ? nb0 + d.n_plain[np + i] / kPlainBatch : 0;
-    const uint4* __restrict__ l8 = reinterpret_cast<const uint4*>(d.nl16) + i;
+    const int nb = STAGED ? nb0 + npl1_ld / kPlainBatch : 0;
     const uint4 zero4 = make_uint4(kHalo | (kHalo << 16), kHalo | (kHalo << 16), kHalo | (kHalo << 16),
                                    kHalo | (kHalo << 16));
-    const int last_blk = d.K / kPlainBatch - 1;
-    // offset (in uint4) of batch b of the sequence from l8
-    auto boff = [&](int b) -> size_t {
-      const int sub = b < nb0 ? 0 : 1;
-      const int blk = min(b - sub * nb0, last_blk);
-      return (size_t)blk * np2 + (size_t)sub * np;
-    };
-    uint4 t0 = l8[boff(half)];
-    uint4 t1 = l8[boff(half + 2)];
     uint4 v0 = nb > half ? t0 : zero4;
     uint4 v1 = nb > half + 2 ? t1 : zero4;
     for (int b = half; b < nb; b += 2) {
@@ -1145,21 +1161,20 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
   double v2 = 0.0;
   if (MODE == kForcesOnly) {
     if (ep) {
-      int t = d.tag[ac][i];
+      int t = tag_ld;
       if (f_out) {
         f_out[t] = fx; f_out[d.n + t] = fy; f_out[2 * d.n + t] = fz;
       }
-      const double* U = d.vel[ac];
-      double cx = U[i] - d.shear_rate * (pi.y - 0.5 * d.Ly);
-      double cy = U[np + i], cz = U[2 * np + i];
+      double cx = u0_ld - d.shear_rate * (pi.y - 0.5 * d.Ly);
+      double cy = u1_ld, cz = u2_ld;
       double m = d.mass;
       kin[0] = m * cx * cx; kin[1] = m * cy * cy; kin[2] = m * cz * cz;
       kin[3] = m * cx * cy; kin[4] = m * cx * cz; kin[5] = m * cy * cz;
     }
   } else if (ep) {
     double* U = d.vel[ac];
-    double ux = U[i], uy = U[np + i], uz = U[2 * np + i];
-    int t = d.tag[ac][i];
+    double ux = u0_ld, uy = u1_ld, uz = u2_ld;
+    int t = tag_ld;
     uint32_t ctr[4] = {(uint32_t)(uint64_t)c->step, (uint32_t)((uint64_t)c->step >> 32), (uint32_t)t, 0u};
     philox(ctr, d.seed_lo, d.seed_hi);
     double cx = ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
