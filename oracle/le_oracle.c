@@ -31,11 +31,12 @@ typedef struct {
     double eps, sigma, rc;
     double fene_k, fene_r0;
     double lj_shift;    /* energy shift added to every pair inside rc (energy only) */
+    double dpd_rc;      /* DPD weight-function cutoff (thermostat 1) */
     uint64_t seed;
     int64_t n;
     int64_t n_chains;
     int32_t chain_len;  /* 0 => no bonds */
-    int32_t pad_;
+    int32_t thermostat; /* 0 Langevin on the peculiar velocity, 1 DPD, 2 Langevin on the lab velocity */
 } orc_params;
 
 enum { ORC_OK = 0, ORC_E_BOND = -4, ORC_E_NONFINITE = -5, ORC_E_ARG = -1 };
@@ -464,17 +465,71 @@ void orc_noise(uint64_t seed, int64_t step, int64_t tag, double theta[3])
     for (int a = 0; a < 3; ++a) theta[a] = ((double)r[a] + 0.5) * (1.0 / 4294967296.0) - 0.5;
 }
 
+/* Uniform pair noise of the DPD random force (Eq. random): one Philox block */
+/* per unordered pair and step, counter (step lo, step hi, smaller tag,      */
+/* larger tag), key (seed lo, seed hi xor 0x44504421) so that the stream is  */
+/* apart from the per-particle Langevin noise; word 0 maps to (-1/2, 1/2).   */
+double orc_dpd_theta(uint64_t seed, int64_t step, int64_t ti, int64_t tj)
+{
+    int64_t a = ti < tj ? ti : tj, b = ti < tj ? tj : ti;
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)step), (uint32_t)((uint64_t)step >> 32), (uint32_t)a,
+                       (uint32_t)b};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x44504421u};
+    uint32_t r[4];
+    orc_philox(ctr, key, r);
+    return ((double)r[0] + 0.5) * (1.0 / 4294967296.0) - 0.5;
+}
+
+/* DPD thermostat (Eqs. dissipative, random, omega), read as the standard    */
+/* pairwise form: for every pair with r < dpd_rc, with e = d/r the unit       */
+/* displacement from j's image to i, v_ij = u_i - u_j - s_y gamma_dot L_y e_x */
+/* the velocity of i relative to that image (an image one box up streams     */
+/* faster by gamma_dot L_y) and w = 1 - r/dpd_rc,                             */
+/*   F_i += [-gamma w^2 (e . v_ij) + sqrt(24 gamma kT / dt) w theta_ij] e,     */
+/*   F_j -= the same.                                                          */
+/* The total force is F^c plus these pair terms only (no per-particle drag). */
+static void thermostat_dpd(int64_t n, const double *x, const double *u, const double *Fc,
+                           double *F, int64_t step, double Delta, const orc_params *p)
+{
+    const double sv = p->shear_rate * p->box[1];
+    const double rd2 = p->dpd_rc * p->dpd_rc;
+    const double pref = sqrt(24.0 * p->gamma * p->kT / p->dt);
+    for (int64_t k = 0; k < 3 * n; ++k) F[k] = Fc[k];
+    double d[3];
+    int32_t img[3];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double r2 = orc_disp(x, n, i, j, Delta, p->box, d, img);
+            if (!(r2 < rd2)) continue;
+            double r = sqrt(r2);
+            double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+            double v[3] = {(u[i] - u[j]) - (double)img[1] * sv, u[n + i] - u[n + j],
+                           u[2 * n + i] - u[2 * n + j]};
+            double w = 1.0 - r / p->dpd_rc;
+            double ev = e[0] * v[0] + e[1] * v[1];
+            ev = ev + e[2] * v[2];
+            double f = -p->gamma * w * w * ev + pref * w * orc_dpd_theta(p->seed, step, i, j);
+            for (int a = 0; a < 3; ++a) {
+                F[a * n + i] += f * e[a];
+                F[a * n + j] -= f * e[a];
+            }
+        }
+}
+
 /* Eq. langevin with the friction acting on the peculiar velocity           */
 /* c = u - shear_rate (y - L_y/2) e_x (Eqs. shear-rate, vi): the total force  */
 /* on one particle is F^c - gamma m c + sqrt(24 gamma m kT / dt) theta.       */
+/* Thermostat 2 applies the friction to the lab velocity u instead (the      */
+/* paper's xi_abs, Section 3.2), which drags the flow profile.               */
 static void thermostat(int64_t n, const double *x, const double *u, const double *Fc,
                        double *F, int64_t step, const orc_params *p)
 {
     const double Ly = p->box[1];
     const double pref = sqrt(24.0 * p->gamma * p->mass * p->kT / p->dt);
+    const double sr = p->thermostat == 2 ? 0.0 : p->shear_rate;
     for (int64_t i = 0; i < n; ++i) {
         double c[3];
-        c[0] = u[i] - p->shear_rate * (x[n + i] - 0.5 * Ly);
+        c[0] = u[i] - sr * (x[n + i] - 0.5 * Ly);
         c[1] = u[n + i];
         c[2] = u[2 * n + i];
         double th[3];
@@ -524,7 +579,8 @@ int orc_step(int64_t n, double *x, double *u, double *F, int64_t *step, const or
     double *Fc = Fc_out ? Fc_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, W6, NULL);
     if (rc != ORC_OK) { if (!Fc_out) free(Fc); return rc; }
-    thermostat(n, x, u, Fc, F, s, p);
+    if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, s, Delta, p);
+    else thermostat(n, x, u, Fc, F, s, p);
     for (int64_t k = 0; k < 3 * n; ++k) u[k] = u[k] + h * F[k];
     for (int64_t k = 0; k < 3 * n; ++k)
         if (!isfinite(x[k]) || !isfinite(u[k])) { if (!Fc_out) free(Fc); return ORC_E_NONFINITE; }
@@ -542,7 +598,10 @@ int orc_init(int64_t n, double *x, double *u, double *F, int64_t step0, const or
     orc_le_wrap(n, x, u, Delta, p);
     double *Fc = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, NULL, NULL);
-    if (rc == ORC_OK) thermostat(n, x, u, Fc, F, step0, p);
+    if (rc == ORC_OK) {
+        if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, step0, Delta, p);
+        else thermostat(n, x, u, Fc, F, step0, p);
+    }
     free(Fc);
     return rc;
 }

@@ -43,12 +43,15 @@ class Params(C.Structure):
         ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("fene_k", C.c_double), ("fene_r0", C.c_double),
         ("lj_shift", C.c_double),
+        ("dpd_rc", C.c_double),
         ("seed", C.c_uint64),
         ("n", C.c_int64),
         ("n_chains", C.c_int64),
         ("chain_len", C.c_int32),
-        ("pad_", C.c_int32),
+        ("thermostat", C.c_int32),
     ]
+
+THERMOSTATS = {"langevin": 0, "dpd": 1, "langevin_abs": 2}
 
 
 _lib = None
@@ -89,6 +92,8 @@ def lib():
         L.orc_philox.restype = None
         L.orc_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int64, dp]
         L.orc_noise.restype = None
+        L.orc_dpd_theta.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64]
+        L.orc_dpd_theta.restype = C.c_double
         L.orc_stress.argtypes = [C.c_int64, dp, dp, dp, pp, dp]
         L.orc_stress.restype = None
         L.orc_step.argtypes = [C.c_int64, dp, dp, dp, i64p, pp, C.c_int, dp, dp]
@@ -122,7 +127,8 @@ class OracleError(RuntimeError):
 
 def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, pair="lj",
                 eps=1.0, sigma=1.0, rc=2.5, fene_k=30.0, fene_r0=1.5, lj_shift=0.0,
-                seed=1, chain_len=0, n_chains=0, **_ignored) -> Params:
+                seed=1, chain_len=0, n_chains=0, thermostat="langevin", dpd_rc=0.0,
+                **_ignored) -> Params:
     p = Params()
     for a in range(3):
         p.box[a] = float(box[a])
@@ -135,7 +141,13 @@ def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, p
     p.n = n
     p.chain_len = chain_len
     p.n_chains = n_chains
+    p.thermostat = THERMOSTATS[thermostat] if isinstance(thermostat, str) else int(thermostat)
+    p.dpd_rc = dpd_rc if dpd_rc > 0 else rc
     return p
+
+
+def dpd_theta(seed, step, ti, tj):
+    return lib().orc_dpd_theta(seed & 0xFFFFFFFFFFFFFFFF, int(step), int(ti), int(tj))
 
 
 def lj_energy_shift(rc, eps=1.0, sigma=1.0):
