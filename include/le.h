@@ -79,6 +79,18 @@ typedef int32_t le_status;
 #define LE_MIXED 1 /* pair-force arithmetic in float32 after a float64 cutoff test;
                       positions, offset, bonds, sums and integrator in float64      */
 
+/* Thermostats (Section 2.2).  theta is uniform on (-1/2, 1/2) from Philox4x32-10. */
+#define LE_THERMO_LANGEVIN 0 /* Eq. langevin on the peculiar velocity c = u - gamma_dot (y - L_y/2) e_x:
+                                F_i += -gamma m c_i + sqrt(24 gamma m kT / dt) theta_i          */
+#define LE_THERMO_DPD 1      /* Eqs. dissipative, random, omega, pairwise for r < dpd_rc with
+                                e = r_ij / r, v_ij = u_i - u_j minus the streaming velocity of
+                                j's image (s_y gamma_dot L_y e_x), w = 1 - r / dpd_rc:
+                                F_i += [-gamma w^2 (e . v_ij) + sqrt(24 gamma kT / dt) w theta_ij] e,
+                                F_j -= the same; theta_ij shared by the pair.  Conserves momentum.
+                                Requires the global-memory pair layout (tune 0 or 2).           */
+#define LE_THERMO_LANGEVIN_LAB 2 /* Eq. langevin with the friction on the lab velocity u (the
+                                paper's xi_abs, Section 3.2): F_i += -gamma m u_i + noise       */
+
 /* Parameters of one simulation (Sections 2.1, 2.2, 2.4).  All 8-byte fields
  * come first so that the layout has no padding. */
 typedef struct le_params {
@@ -94,6 +106,8 @@ typedef struct le_params {
   double skin;         /* Verlet skin (>= 0); 0 rebuilds and wraps every step       */
   double fene_k;       /* FENE spring constant k                                    */
   double fene_r0;      /* FENE maximal bond length R0                               */
+  double dpd_rc;       /* cutoff r_c of the DPD weight omega (Eq. omega); 0 = rc;
+                          must not exceed rc (the pair list covers rc only)      */
   int64_t n_chains;    /* linear chains: tag = chain*chain_len + k; 0 = no bonds    */
   uint64_t seed;       /* Philox key of the thermostat noise                        */
   int32_t chain_len;   /* beads per chain (0 = no bonds)                            */
@@ -105,6 +119,8 @@ typedef struct le_params {
   int32_t tune;        /* pair-kernel layout: 0 = chosen from density, 1 = partners staged
                           in an LDS halo per tile, 2 = partners read from global memory;
                           the physics is the same (sums may differ in the last bits) */
+  int32_t thermostat;  /* LE_THERMO_*: how gamma and kT act (Section 2.2)                */
+  int32_t reserved;    /* must be 0                                                      */
 } le_params;
 
 /* Device bytes needed for a simulation with these parameters.  Pure host
@@ -116,7 +132,7 @@ le_status le_workspace_bytes(const le_params* p, size_t* bytes);
  * (they are wrapped with the offset of step0, Eq. pos_new), u0 are lab-frame
  * velocities.  f0: NULL, or the device float64 [3][n] total force of step
  * step0 as returned by le_get_state (exact restart); when NULL the force of
- * step0 (conservative + Langevin with the noise of step0, evaluated at u0) is
+ * step0 (conservative + thermostat with the noise of step0, evaluated at u0) is
  * computed here.  workspace: device buffer of ws_bytes >=
  * le_workspace_bytes(p).  hip_stream: a hipStream_t (NULL = the null
  * stream).  *out receives the handle. */
@@ -235,8 +251,10 @@ le_status le_offsets(double shear_rate, double Lx, double Ly, double dt, int64_t
 
 /* Philox4x32-10 blocks as the thermostat draws them: for each k, counter
  * ctr[4k..4k+3] and key key[2k..2k+1] (device uint32) give out[4k..4k+3]
- * (device uint32).  The thermostat of step s uses counter (s lo, s hi, tag,
- * 0) and key (seed lo, seed hi); word a maps to (r_a + 1/2) 2^-32 - 1/2. */
+ * (device uint32).  The Langevin thermostat of step s uses counter (s lo,
+ * s hi, tag, 0) and key (seed lo, seed hi); word a maps to (r_a + 1/2) 2^-32
+ * - 1/2.  The DPD pair noise of step s uses counter (s lo, s hi, smaller tag,
+ * larger tag), key (seed lo, seed hi xor 0x44504421) and word 0. */
 le_status le_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
                     void* hip_stream);
 

@@ -26,6 +26,9 @@ LE_PAIR_LJ = 0
 LE_PAIR_WCA = 1
 LE_FP64 = 0
 LE_MIXED = 1
+LE_THERMO_LANGEVIN = 0
+LE_THERMO_DPD = 1
+LE_THERMO_LANGEVIN_LAB = 2
 
 EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
@@ -52,6 +55,7 @@ class le_params(C.Structure):
         ("skin", C.c_double),
         ("fene_k", C.c_double),
         ("fene_r0", C.c_double),
+        ("dpd_rc", C.c_double),
         ("n_chains", C.c_int64),
         ("seed", C.c_uint64),
         ("chain_len", C.c_int32),
@@ -60,6 +64,8 @@ class le_params(C.Structure):
         ("cells", C.c_int32 * 3),
         ("max_neighbors", C.c_int32),
         ("tune", C.c_int32),
+        ("thermostat", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -64,8 +64,15 @@ le_status validate(const le_params* p, Geometry* g) {
   if (p->pair != LE_PAIR_LJ && p->pair != LE_PAIR_WCA) return LE_E_ARG;
   if (p->precision != LE_FP64 && p->precision != LE_MIXED) return LE_E_ARG;
   if (p->tune < 0 || p->tune > 2) return LE_E_ARG;
+  if (p->thermostat < LE_THERMO_LANGEVIN || p->thermostat > LE_THERMO_LANGEVIN_LAB) return LE_E_ARG;
+  if (p->reserved != 0) return LE_E_ARG;
   double rc = p->rc;
   if (rc <= 0.0) rc = (p->pair == LE_PAIR_WCA) ? pow(2.0, 1.0 / 6.0) * p->sigma : 2.5 * p->sigma;
+  if (p->thermostat == LE_THERMO_DPD) {
+    // the pair terms run over the neighbour lists (radius rc + skin, valid
+    // for r < rc), in the global-memory layout
+    if (!(p->dpd_rc >= 0.0) || p->dpd_rc > rc || p->tune == 1) return LE_E_ARG;
+  }
   if (p->chain_len < 0 || p->n_chains < 0) return LE_E_ARG;
   if (p->n_chains > 0) {
     if (p->chain_len < 2 || p->n_chains * (int64_t)p->chain_len > p->n) return LE_E_ARG;
@@ -183,6 +190,14 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->h = 0.5 * p->dt / p->mass;
   d->gamma_m = p->gamma * p->mass;
   d->pref = sqrt(24.0 * p->gamma * p->mass * p->kT / p->dt);
+  d->thermostat = p->thermostat;
+  {
+    const double dpd_rc = p->dpd_rc > 0.0 ? p->dpd_rc : g.rc;
+    d->dpd_gamma = p->gamma;
+    d->dpd_pref = sqrt(24.0 * p->gamma * p->kT / p->dt);
+    d->dpd_rc2 = dpd_rc * dpd_rc;
+    d->dpd_inv_rc = 1.0 / dpd_rc;
+  }
   d->mass = p->mass;
   d->eps24 = 24.0 * p->eps;
   d->sig2 = p->sigma * p->sigma;
@@ -219,6 +234,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->precision = p->precision;
   d->seed_lo = (uint32_t)p->seed;
   d->seed_hi = (uint32_t)(p->seed >> 32);
+  d->dpd_key_hi = d->seed_hi ^ 0x44504421u;
   d->nblocks = g.nblocks;
   d->ntiles = g.nblocks;
   d->bcap = g.bcap;
@@ -232,6 +248,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
     const double halo_pp = 9.0 * (tile_cells + 2.0) * cell_n / kTile;
     const double list_pp = 4.0 / 3.0 * M_PI * g.rlist * g.rlist * g.rlist * rho;
     d->staged = (p->tune == 1) ? 1 : (p->tune == 2) ? 0 : (list_pp >= 3.0 * halo_pp ? 1 : 0);
+    if (p->thermostat == LE_THERMO_DPD) d->staged = 0;
   }
 }
 
@@ -343,7 +360,9 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   double Delta0 = le_offset(step0, p->dt, s->d.sv, p->box[0]);
   st = hip_check(launch_load_state(s->d, s->stream, x0, u0, f0, step0, Delta0));
   if (st == LE_OK) st = rebuild(s, true, false);
-  if (st == LE_OK && !f0) st = hip_check(launch_force(s->d, s->stream, kInitForce, false, nullptr, nullptr));
+  if (st == LE_OK && !f0)
+    st = hip_check(launch_force(s->d, s->stream, s->d.thermostat == LE_THERMO_DPD ? kDpdForce : kInitForce,
+                                false, nullptr, nullptr));
   if (st != LE_OK) {
     delete s;
     return st;
@@ -411,7 +430,21 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
     // phase 0: the fused force kernel of plain steps, timed by the dispatch
     // itself; phase 3: sampled steps (force kernel with the virial, then the
     // stress reduction)
-    if (sample) {
+    if (d.thermostat == LE_THERMO_DPD) {
+      // pair thermostat: all forces first, then the kicks and drift
+      ev = sample ? begin_phase(s, 3) : -1;
+      long ef = (!sample && s->tick++ % s->timing_stride == 0) ? reserve_pair(s, 0) : -1;
+      st = hip_check(launch_force(d, q, kDpdForce, sample, nullptr, nullptr, ef >= 0 ? s->ev[2 * ef] : nullptr,
+                                  ef >= 0 ? s->ev[2 * ef + 1] : nullptr));
+      if (ef >= 0) s->ev_used = (size_t)ef + 1;
+      if (st == LE_OK) st = hip_check(launch_integrate(d, q, last, sample));
+      if (st == LE_OK && sample) {
+        double* slot = stress_ring + 6 * (ns % ring_cap);
+        ++ns;
+        st = hip_check(launch_stress_final(d, q, slot, false));
+      }
+      end_phase(s, ev);
+    } else if (sample) {
       ev = begin_phase(s, 3);
       st = hip_check(launch_force(d, q, last ? kStepLast : kStepFused, true, nullptr, nullptr));
       if (st == LE_OK) {

@@ -60,6 +60,8 @@ struct Dev {
   double dt, h;                    // time step and dt / (2 m)
   double gamma_m;                  // gamma * m
   double pref;                     // sqrt(24 gamma m kT / dt)
+  double dpd_gamma, dpd_pref;      // DPD: gamma and sqrt(24 gamma kT / dt)
+  double dpd_rc2, dpd_inv_rc;      // DPD: r_c^2 and 1 / r_c of the weight omega
   double mass;
   double eps24, sig2;              // 24 eps, sigma^2
   double rc2, rlist, rlist2;       // cutoff^2, list radius, list radius^2
@@ -78,6 +80,8 @@ struct Dev {
   // outside; in between the plain FP64 displacement decides.
   float nb_lo, nb_hi;
   uint32_t seed_lo, seed_hi;
+  uint32_t dpd_key_hi;             // seed_hi ^ 0x44504421: key word of the DPD pair noise
+  int32_t thermostat;              // LE_THERMO_*
   int32_t nblocks;                 // blocks of the pair kernels (= ntiles)
   // buffers (device)
   double* pos[2];                  // double4 [np] each (x, y, z, unused)
@@ -132,7 +136,7 @@ __host__ __device__ inline void unpack_img(uint8_t c, int& sx, int& sy, int& sz)
 
 // Launchers (le_kernels.hip).  Each enqueues on `stream` and returns the
 // hipError_t of the launch.
-enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 };
+enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3, kDpdForce = 4 };
 
 // launch_rebuild reads control copy d.ctrl and writes `next`, which the
 // following launches must then be given.  control: advance the step first
@@ -140,6 +144,10 @@ enum ForceMode { kForcesOnly = 0, kStepFused = 1, kStepLast = 2, kInitForce = 3 
 hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vmax, hipStream_t s,
                           bool force, bool control);
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s);
+// DPD steps: the force kernel (kDpdForce) only writes the total force; this
+// kernel then applies the second half-kick (and, unless last, the next
+// half-kick and drift), with kinetic stress partials when sample is set.
+hipError_t launch_integrate(const Dev& d, hipStream_t s, bool last, bool sample);
 hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample, double* f_out,
                         double* sample_out, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);

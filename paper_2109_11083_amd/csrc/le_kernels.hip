@@ -920,9 +920,33 @@ __device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, 
   }
 }
 
+// DPD pair terms (Eqs. dissipative, random, omega) on particle i from one
+// partner: d = x_i - x_j(image), v = u_i - u_j(image) (the image's streaming
+// velocity already removed), r2 = |d|^2.  Adds f d with
+// f = [-gamma w^2 (d.v / r) + sqrt(24 gamma kT / dt) w theta_ij] / r,
+// w = 1 - r / r_c, zero at and beyond r_c.  theta_ij is word 0 of the Philox
+// block with counter (step, smaller tag, larger tag), so both members of the
+// pair draw the same number and their forces cancel.
+__device__ __forceinline__ void dpd_pair(const Dev& d, uint32_t s_lo, uint32_t s_hi, int ti, int tj,
+                                         double vx, double vy, double vz, double dx, double dy,
+                                         double dz, double r2, double& ax, double& ay, double& az) {
+  const bool in = r2 < d.dpd_rc2;
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r;
+  const double wgt = 1.0 - r * d.dpd_inv_rc;
+  double ev = dx * vx + dy * vy;
+  ev = (ev + dz * vz) * ir;
+  uint32_t c[4] = {s_lo, s_hi, (uint32_t)min(ti, tj), (uint32_t)max(ti, tj)};
+  philox(c, d.seed_lo, d.dpd_key_hi);
+  double f = (-d.dpd_gamma * wgt * wgt * ev + d.dpd_pref * wgt * u01c(c[0])) * ir;
+  f = in ? f : 0.0;
+  ax = fma(f, dx, ax); ay = fma(f, dy, ay); az = fma(f, dz, az);
+}
+
 // Block reduction of 12 per-thread sums into partials[block][12] (fixed
 // order: wave butterflies, then waves in index order).
-__device__ __forceinline__ void block_partials(double* vals, double* out, int lb) {
+__device__ __forceinline__ void block_partials(double* vals, double* out, int lb,
+                                               int nwrite = kStressComps) {
   __shared__ double red[kBlock / 64][kStressComps];  // blockDim.x <= kBlock
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -932,7 +956,7 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
     if (lane == 0) red[wid][k] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kStressComps) {
+  if (threadIdx.x < nwrite) {
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += red[w][threadIdx.x];
     out[lb * kStressComps + threadIdx.x] = s;
@@ -945,8 +969,12 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 //   kInitForce   F = F^c + Langevin(u) of the current step into frc
 //   kStepLast    F as above from the half-step velocity, u += dt/(2m) F
 //   kStepFused   as kStepLast, then the next half-kick and drift
+//   kDpdForce    F = F^c + DPD pair terms of the current (half-step)
+//                velocities into frc; k_integrate then moves the particles
+//                (velocities of partners must not change while it runs)
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
+// (with the friction on the lab velocity, c = u of the image inside the box).
 // With the LDS halo the block has two threads per particle: thread t and
 // t + kTile take alternate batches of the particle's list (twice the waves
 // per CU for the same LDS), and the second hands its partial sums to the
@@ -955,6 +983,8 @@ template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED>
 __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__ f_out,
                                                      double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
+  constexpr bool DPD = MODE == kDpdForce;
+  static_assert(!DPD || !STAGED, "DPD partners come from global memory");
   constexpr int kH = STAGED ? kHalo + 1 : 1;  // no halo: every partner from global memory
   constexpr int kTh = STAGED ? 2 * kTile : kTile;  // threads per block
   static_assert(!STAGED || kHalo + 1 >= kTile * 9, "the halo array holds the partial-sum exchange");
@@ -1040,8 +1070,11 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     __syncthreads();
   }
   double fx = 0.0, fy = 0.0, fz = 0.0;
+  double gx = 0.0, gy = 0.0, gz = 0.0;  // DPD pair terms (kept out of the virial)
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double4 pi = valid ? pi_ld : make_double4(0.0, 0.0, 0.0, 0.0);
+  const uint32_t st_lo = (uint32_t)(uint64_t)c->step, st_hi = (uint32_t)((uint64_t)c->step >> 32);
+  const int* __restrict__ Tg = d.tag[ac];
   if (valid) {
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
     // staged partners (already shifted to their image): the particle's two
@@ -1099,6 +1132,18 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       double4 pj[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) pj[u] = P[sl[u]];
+      // DPD: the partners' tags and velocities (the sentinel's are never used)
+      int tj[DPD ? 8 : 1];
+      double vj[DPD ? 24 : 1];
+      if (DPD) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          tj[u] = Tg[sl[u]];
+          vj[3 * u] = Uv[sl[u]];
+          vj[3 * u + 1] = Uv[np + sl[u]];
+          vj[3 * u + 2] = Uv[2 * np + sl[u]];
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         int sx, sy, sz;
@@ -1110,6 +1155,12 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
         add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+        if (DPD) {
+          // the image s_y boxes up streams faster by s_y gamma_dot L_y
+          const double vx = (u0_ld - vj[3 * u]) - (double)sy * d.sv;
+          dpd_pair(d, st_lo, st_hi, tag_ld, tj[u], vx, u1_ld - vj[3 * u + 1], u2_ld - vj[3 * u + 2],
+                   dx, dy, dz, r2, gx, gy, gz);
+        }
       }
     }
     }
@@ -1171,13 +1222,22 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       kin[0] = m * cx * cx; kin[1] = m * cy * cy; kin[2] = m * cz * cz;
       kin[3] = m * cx * cy; kin[4] = m * cx * cz; kin[5] = m * cy * cz;
     }
+  } else if (DPD) {
+    if (ep) {
+      double* F = d.frc[ac];
+      F[i] = fx + gx; F[np + i] = fy + gy; F[2 * np + i] = fz + gz;
+    }
   } else if (ep) {
     double* U = d.vel[ac];
     double ux = u0_ld, uy = u1_ld, uz = u2_ld;
     int t = tag_ld;
-    uint32_t ctr[4] = {(uint32_t)(uint64_t)c->step, (uint32_t)((uint64_t)c->step >> 32), (uint32_t)t, 0u};
+    uint32_t ctr[4] = {st_lo, st_hi, (uint32_t)t, 0u};
     philox(ctr, d.seed_lo, d.seed_hi);
-    double cx = ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
+    // friction velocity: peculiar (Eq. vi), or the lab velocity of the image
+    // inside the box (positions are wrapped lazily, so a particle above the
+    // top face still carries the velocity it had before crossing)
+    double cx = d.thermostat == LE_THERMO_LANGEVIN_LAB ? ux - d.sv * floor(pi.y / d.Ly)
+                                                       : ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
     double Fx = (fx - d.gamma_m * cx) + d.pref * u01c(ctr[0]);
     double Fy = (fy - d.gamma_m * uy) + d.pref * u01c(ctr[1]);
     double Fz = (fz - d.gamma_m * uz) + d.pref * u01c(ctr[2]);
@@ -1216,6 +1276,60 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
 #pragma unroll
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.5 * w[k]; }
     block_partials(vals, d.partials, lb);
+  }
+}
+
+// DPD steps, after k_force<kDpdForce>: u += dt/(2m) F (the step's second
+// half-kick); with SAMPLE the kinetic stress partials of the new full-step
+// velocities go to partials[block][0..5] (the force kernel wrote the virial
+// to [6..11]); unless LAST, the next half-kick and drift follow as in the
+// fused Langevin step.  One thread per slot, blocks of kTile.
+template <bool LAST, bool SAMPLE>
+__global__ void __launch_bounds__(kTile) k_integrate(Dev d) {
+  __shared__ int skip;
+  Ctrl* c = d.ctrl;
+  if (threadIdx.x == 0) skip = d.flags->status;
+  __syncthreads();
+  if (skip) return;
+  const int i = blockIdx.x * kTile + threadIdx.x;
+  const int np = d.np;
+  double kin[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double v2 = 0.0;
+  if (i < d.n) {
+    const int pc = c->pos_cur, ac = c->aux_cur;
+    const double4 p = reinterpret_cast<const double4*>(d.pos[pc])[i];
+    double* U = d.vel[ac];
+    const double* F = d.frc[ac];
+    const double Fx = F[i], Fy = F[np + i], Fz = F[2 * np + i];
+    double ux = U[i] + d.h * Fx;
+    double uy = U[np + i] + d.h * Fy;
+    double uz = U[2 * np + i] + d.h * Fz;
+    if (SAMPLE) {
+      const double m = d.mass;
+      const double cx = ux - d.shear_rate * (p.y - 0.5 * d.Ly);
+      kin[0] = m * cx * cx; kin[1] = m * uy * uy; kin[2] = m * uz * uz;
+      kin[3] = m * cx * uy; kin[4] = m * cx * uz; kin[5] = m * uy * uz;
+    }
+    if (!LAST) {
+      ux = ux + d.h * Fx; uy = uy + d.h * Fy; uz = uz + d.h * Fz;
+      const double cxh = ux - d.shear_rate * (p.y - 0.5 * d.Ly);
+      v2 = cxh * cxh + uy * uy + uz * uz;
+      double4 q;
+      q.x = p.x + d.dt * ux;
+      q.y = p.y + d.dt * uy;
+      q.z = p.z + d.dt * uz;
+      q.w = p.w;
+      reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
+      if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
+    }
+    U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
+  }
+  if (!LAST) vmax_commit(d, v2);
+  if (SAMPLE) {
+    double vals[kStressComps];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.0; }
+    block_partials(vals, d.partials, blockIdx.x, 6);
   }
 }
 
@@ -1440,6 +1554,23 @@ hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample
       if (sample) launch_force_t<kStepFused, true>(d, s, f_out, sample_out, e0, e1);
       else launch_force_t<kStepFused, false>(d, s, f_out, nullptr, e0, e1);
       break;
+    case kDpdForce:
+      if (d.staged) return hipErrorInvalidValue;  // DPD partners come from global memory
+      if (sample) launch_force_s<kDpdForce, true, false>(d, s, f_out, sample_out, e0, e1);
+      else launch_force_s<kDpdForce, false, false>(d, s, f_out, nullptr, e0, e1);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate(const Dev& d, hipStream_t s, bool last, bool sample) {
+  dim3 g(d.ntiles), b(kTile);
+  if (last) {
+    if (sample) hipLaunchKernelGGL((k_integrate<true, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_integrate<true, false>), g, b, 0, s, d);
+  } else {
+    if (sample) hipLaunchKernelGGL((k_integrate<false, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_integrate<false, false>), g, b, 0, s, d);
   }
   return hipGetLastError();
 }

@@ -15,6 +15,8 @@ from . import binding as B
 
 PAIRS = {"lj": B.LE_PAIR_LJ, "wca": B.LE_PAIR_WCA}
 PRECISIONS = {"fp64": B.LE_FP64, "mixed": B.LE_MIXED}
+THERMOSTATS = {"langevin": B.LE_THERMO_LANGEVIN, "dpd": B.LE_THERMO_DPD,
+               "langevin_abs": B.LE_THERMO_LANGEVIN_LAB}
 
 
 @dataclass
@@ -41,6 +43,8 @@ class Params:
     cells: tuple = (0, 0, 0)
     max_neighbors: int = 0
     tune: int = 0
+    thermostat: str = "langevin"
+    dpd_rc: float = 0.0
 
     def to_c(self) -> B.le_params:
         p = B.le_params()
@@ -58,6 +62,8 @@ class Params:
         p.precision = PRECISIONS[self.precision]
         p.max_neighbors = int(self.max_neighbors)
         p.tune = int(self.tune)
+        p.thermostat = THERMOSTATS[self.thermostat]
+        p.dpd_rc = float(self.dpd_rc)
         return p
 
     @property

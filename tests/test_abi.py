@@ -71,6 +71,26 @@ def test_workspace_bytes_and_geometry_errors():
         with pytest.raises(B.LeError) as e:
             B.le_workspace_bytes(_lj(tune=t).to_c())
         assert e.value.code == B.LE_E_ARG
+    # thermostats: unknown code, DPD with the LDS halo layout or a weight
+    # cutoff beyond the pair cutoff, a non-zero reserved word
+    for bad in (dict(thermostat="dpd", tune=1), dict(thermostat="dpd", dpd_rc=2.6)):
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(_lj(**bad).to_c())
+        assert e.value.code == B.LE_E_ARG, bad
+    for code in (-1, 3):
+        c = _lj().to_c()
+        c.thermostat = code
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(c)
+        assert e.value.code == B.LE_E_ARG
+    c = _lj().to_c()
+    c.reserved = 1
+    with pytest.raises(B.LeError) as e:
+        B.le_workspace_bytes(c)
+    assert e.value.code == B.LE_E_ARG
+    for ok in (dict(thermostat="dpd"), dict(thermostat="dpd", dpd_rc=1.0, tune=2),
+               dict(thermostat="langevin_abs", tune=1)):
+        assert B.le_workspace_bytes(_lj(**ok).to_c()) > 0
 
 
 def test_init_rejects_small_workspace_before_any_device_work():

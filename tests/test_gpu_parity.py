@@ -35,7 +35,7 @@ def e_F(F, Fref):
 def _oracle_params(p: Params, **over):
     kw = dict(shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma, mass=p.mass, eps=p.eps,
               sigma=p.sigma, rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
-              chain_len=p.chain_len, n_chains=p.n_chains)
+              chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc)
     kw.update(over)
     return O.make_params(p.n, p.box, **kw)
 

@@ -1,0 +1,193 @@
+"""GPU parity of the DPD thermostat and of the Langevin friction on the lab
+velocity (Section 2.2; xi_DPD and xi_abs of Section 3.2) against the oracle.
+
+DPD pair sums are accumulated in list order on the GPU and in (i, j) order in
+the oracle, so forces agree to rounding (1e-12 relative to the force scale)
+and trajectories to the chaotic growth of that rounding over 100 steps.  The
+lab-velocity friction with a rebuild every step reproduces the oracle bit for
+bit, as the peculiar one does.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2109_11083_amd import binding as B
+from paper_2109_11083_amd import inputs
+from paper_2109_11083_amd.sim import Params, Sim
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_params(p: Params):
+    return O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma, mass=p.mass,
+                         eps=p.eps, sigma=p.sigma, rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
+                         chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc)
+
+
+def e_F(F, Fref):
+    rms = math.sqrt(float((Fref ** 2).sum(axis=0).mean()))
+    return float(np.sqrt(((F - Fref) ** 2).sum(axis=0)).max()) / rms
+
+
+def _lj(shear_rate=0.5, seed=11, n_side=10, **kw):
+    w = inputs.lj_workload(n_side=n_side, shear_rate=shear_rate, seed=seed)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, **kw)
+    return w, p
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+@pytest.mark.parametrize("step0", [0, 7919])
+def test_dpd_initial_force(precision, tol, step0):
+    """Total force of the initial state: LJ + DPD dissipative and random pair
+    terms with the velocities of the input (image velocities shifted across
+    the sheared faces), the noise of step0."""
+    w, p = _lj(thermostat="dpd", gamma=5.0, skin=0.3, precision=precision)
+    _log(f"dpd init force {precision} step0={step0}")
+    sim = Sim(p, w.x, w.u, step0=step0)
+    ref = O.Sim(w.x, w.u, _oracle_params(p), step0=step0)
+    _, _, gf, st = sim.state()
+    assert st == step0
+    err = e_F(gf, ref.F)
+    _log(f"  e_F={err:.3e}")
+    assert err <= tol
+    sim.close()
+
+
+@pytest.mark.parametrize("skin,dpd_rc", [(0.0, 0.0), (0.3, 0.0), (0.3, 1.2)])
+def test_dpd_lj_trajectory_100_steps(skin, dpd_rc):
+    w, p = _lj(thermostat="dpd", gamma=5.0, skin=skin, dpd_rc=dpd_rc)
+    _log(f"dpd trajectory skin={skin} dpd_rc={dpd_rc}")
+    sim = Sim(p, w.x, w.u, step0=0)
+    ref = O.Sim(w.x, w.u, _oracle_params(p), step0=0)
+    ring = sim.step(100, sample_every=10)
+    sref = ref.run(100, sample_every=10)
+    gx, gu, gf, st = sim.state()
+    assert st == 100 == ref.step
+    L = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - L * np.round(dx / L)
+    cg = gu[0] - p.shear_rate * (gx[1] - p.box[1] / 2)
+    cr = ref.u[0] - p.shear_rate * (ref.x[1] - p.box[1] / 2)
+    _log(f"  max|dx|={np.abs(dx).max():.3e} max|dc|={np.abs(cg - cr).max():.3e}")
+    assert np.abs(dx).max() < 1e-8
+    assert np.abs(cg - cr).max() < 1e-7
+    assert np.abs(gu[1:] - ref.u[1:]).max() < 1e-7
+    sg = ring.cpu().numpy()
+    scale = np.abs(sref[:, :3]).max()
+    assert np.abs(sg - sref).max() / scale < 1e-9
+    sim.close()
+
+
+def test_dpd_kg_trajectory():
+    """Bonded chains (WCA + FENE) with DPD: bonds stay in the conservative
+    force, DPD acts on every pair within the WCA cutoff."""
+    n_chains, chain_len = 20, 20
+    w = inputs.kg_workload(n_chains, chain_len, shear_rate=0.05, seed=31)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.05, seed=31, rc=2 ** (1 / 6), pair="wca",
+               n_chains=n_chains, chain_len=chain_len, gamma=5.0, dt=0.005, skin=0.4, thermostat="dpd")
+    _log("dpd kg trajectory")
+    sim = Sim(p, w.x, w.u)
+    ref = O.Sim(w.x, w.u, _oracle_params(p))
+    sim.step(60)
+    ref.run(60)
+    gx, gu, gf, st = sim.state()
+    L = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - L * np.round(dx / L)
+    _log(f"  max|dx|={np.abs(dx).max():.3e}")
+    assert np.abs(dx).max() < 1e-8
+    assert e_F(gf, ref.F) < 1e-7
+    sim.close()
+
+
+def test_dpd_conserves_momentum_on_gpu():
+    """No shear: the pair terms cancel, so the total momentum stays at its
+    initial value up to the rounding of the sums."""
+    w, p = _lj(shear_rate=0.0, thermostat="dpd", gamma=25.0, kT=1.5, skin=0.3)
+    sim = Sim(p, w.x, w.u)
+    _, u0, _, _ = sim.state()
+    P0 = u0.sum(axis=1)
+    sim.step(300)
+    _, u1, f1, _ = sim.state()
+    P1 = u1.sum(axis=1)
+    _log(f"dpd momentum drift {np.abs(P1 - P0).max():.3e}")
+    assert np.abs(P1 - P0).max() < 1e-9 * w.x.shape[1]
+    assert np.abs(f1.sum(axis=1)).max() < 1e-9 * w.x.shape[1]
+    sim.close()
+
+
+def test_dpd_graph_replays_match_eager():
+    w, p = _lj(shear_rate=0.4, thermostat="dpd", gamma=5.0, skin=0.3)
+    a = Sim(p, w.x, w.u)
+    sb = torch.cuda.Stream()
+    b = Sim(p, w.x, w.u, stream=sb)
+    ring_a = torch.zeros((5, 6), dtype=torch.float64, device=DEV)
+    with torch.cuda.stream(sb):
+        ring_b = torch.zeros((5, 6), dtype=torch.float64, device=DEV)
+    sb.synchronize()
+    g = b.graph(50, sample_every=10, ring=ring_b)
+    for rep in range(3):
+        a.step(50, sample_every=10, ring=ring_a)
+        g.launch()
+        b.sync()
+        xa, ua, fa, sta = a.state()
+        xb, ub, fb, stb = b.state()
+        assert sta == stb
+        assert np.array_equal(xa, xb) and np.array_equal(ua, ub) and np.array_equal(fa, fb), rep
+        torch.cuda.synchronize()
+        assert torch.equal(ring_a, ring_b), rep
+    g.close()
+    a.close()
+    b.close()
+
+
+def test_lab_langevin_ideal_gas_bitwise_skin0():
+    rng = np.random.default_rng(4)
+    n, L = 500, 9.0
+    x = rng.uniform(0, L, size=(3, n))
+    c = inputs.maxwell(n, 1.0, 1.0, 5)
+    u = inputs.streaming_initial_velocity(x, c, 0.9, L)
+    p = Params(n=n, box=(L, L, L), shear_rate=0.9, eps=0.0, rc=1.0, skin=0.0, gamma=1.3, kT=1.1,
+               dt=0.01, seed=77, thermostat="langevin_abs")
+    sim = Sim(p, x, u, step0=3)
+    ref = O.Sim(x, u, _oracle_params(p), step0=3)
+    for _ in range(3):
+        sim.step(50)
+        ref.run(50)
+        gx, gu, gf, st = sim.state()
+        assert st == ref.step
+        assert np.array_equal(gx, ref.x)
+        assert np.array_equal(gu, ref.u)
+        assert np.array_equal(gf, ref.F)
+    sim.close()
+
+
+def test_lab_langevin_lj_trajectory_lazy_wrap():
+    """With a skin the particles are wrapped only at rebuilds; the friction
+    must still act on the lab velocity of the in-box image."""
+    w, p = _lj(shear_rate=0.5, thermostat="langevin_abs", gamma=1.0, skin=0.3)
+    sim = Sim(p, w.x, w.u)
+    ref = O.Sim(w.x, w.u, _oracle_params(p))
+    ring = sim.step(100, sample_every=20)
+    sref = ref.run(100, sample_every=20)
+    gx, gu, gf, st = sim.state()
+    L = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - L * np.round(dx / L)
+    _log(f"lab langevin max|dx|={np.abs(dx).max():.3e} rebuilds={sim.stats()['rebuilds']}")
+    assert sim.stats()["rebuilds"] < 100
+    assert np.abs(dx).max() < 1e-8
+    sg = ring.cpu().numpy()
+    assert np.abs(sg - sref).max() / np.abs(sref[:, :3]).max() < 1e-9
+    sim.close()
