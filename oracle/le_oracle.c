@@ -628,16 +628,19 @@ int orc_run(int64_t n, double *x, double *u, double *F, int64_t *step, const orc
 }
 
 /* O12. Observables of a state: nbins-bin profiles along the gradient axis of */
-/* the particle count and of the summed flow velocity (Fig. profile), using   */
-/* the wrapped y and the lab u_x of the wrapped image; kinetic temperature of */
-/* the peculiar velocities sum m c^2 / (3N - 3); centre-of-mass lab velocity. */
+/* the particle count, of the summed flow velocity (Fig. profile) and of the  */
+/* summed peculiar kinetic term m c^2 (the temperature profile, three times   */
+/* kT per particle in equilibrium), using the wrapped y and the lab u_x of    */
+/* the wrapped image; kinetic temperature of the peculiar velocities          */
+/* sum m c^2 / (3N - 3); centre-of-mass lab velocity.                         */
 void orc_observables(int64_t n, const double *x, const double *u, double Delta, const orc_params *p,
-                     int32_t nbins, double *count, double *sum_ux, double *kT_kin, double com[3])
+                     int32_t nbins, double *count, double *sum_ux, double *sum_mc2, double *kT_kin,
+                     double com[3])
 {
     const double Ly = p->box[1];
     const double sv = p->shear_rate * Ly;
     (void)Delta;
-    for (int32_t b = 0; b < nbins; ++b) { count[b] = 0.0; sum_ux[b] = 0.0; }
+    for (int32_t b = 0; b < nbins; ++b) { count[b] = 0.0; sum_ux[b] = 0.0; sum_mc2[b] = 0.0; }
     double k2 = 0.0;
     com[0] = com[1] = com[2] = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -650,8 +653,10 @@ void orc_observables(int64_t n, const double *x, const double *u, double Delta, 
         count[b] += 1.0;
         sum_ux[b] += ux;
         double cx = u[i] - p->shear_rate * (x[n + i] - 0.5 * Ly);
-        k2 += p->mass * (cx * cx + u[n + i] * u[n + i] + u[2 * n + i] * u[2 * n + i]);
-        com[0] += u[i]; com[1] += u[n + i]; com[2] += u[2 * n + i];
+        double mc2 = p->mass * (cx * cx + u[n + i] * u[n + i] + u[2 * n + i] * u[2 * n + i]);
+        sum_mc2[b] += mc2;
+        k2 += mc2;
+        com[0] += ux; com[1] += u[n + i]; com[2] += u[2 * n + i];
     }
     *kT_kin = k2 / (3.0 * (double)n - 3.0);
     for (int a = 0; a < 3; ++a) com[a] /= (double)n;

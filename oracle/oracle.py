@@ -102,7 +102,7 @@ def lib():
         L.orc_init.restype = C.c_int
         L.orc_run.argtypes = [C.c_int64, dp, dp, dp, i64p, pp, C.c_int, C.c_int64, C.c_int64, dp]
         L.orc_run.restype = C.c_int
-        L.orc_observables.argtypes = [C.c_int64, dp, dp, C.c_double, pp, C.c_int32, dp, dp, dp, dp]
+        L.orc_observables.argtypes = [C.c_int64, dp, dp, C.c_double, pp, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_observables.restype = None
         L.orc_energy.argtypes = [C.c_int64, dp, C.c_double, pp, dp]
         L.orc_energy.restype = C.c_int
@@ -277,11 +277,19 @@ def observables(x, u, Delta, p: Params, nbins=50):
     x, u = _c64(x), _c64(u)
     cnt = np.zeros(nbins)
     sux = np.zeros(nbins)
+    smc2 = np.zeros(nbins)
     kt = C.c_double(0.0)
     com = np.zeros(3)
     lib().orc_observables(x.shape[1], _dp(x), _dp(u), Delta, C.byref(p), nbins, _dp(cnt), _dp(sux),
-                          C.byref(kt), _dp(com))
-    return dict(count=cnt, sum_ux=sux, kT=kt.value, com=com)
+                          _dp(smc2), C.byref(kt), _dp(com))
+    return dict(count=cnt, sum_ux=sux, sum_mc2=smc2, kT=kt.value, com=com)
+
+
+def msd(unw, ref):
+    """Mean squared displacement along y and z of unwrapped coordinates
+    [2][n] relative to ref [2][n]."""
+    d = np.asarray(unw) - np.asarray(ref)
+    return (d ** 2).mean(axis=1)
 
 
 class Sim:
@@ -315,6 +323,20 @@ class Sim:
         if rc != 0:
             raise OracleError(rc)
         return out[:ns]
+
+    def run_tracked(self, nsteps, unw):
+        """Run nsteps one at a time and add each particle's per-step change of
+        y and z, taken as the minimum image (a particle moves far less than half
+        a box in one step), to unw [2][n]: the unwrapped gradient and vorticity
+        coordinates.  Returns unw."""
+        Ly, Lz = self.p.box[1], self.p.box[2]
+        for _ in range(nsteps):
+            y0, z0 = self.x[1].copy(), self.x[2].copy()
+            self.run(1)
+            dy, dz = self.x[1] - y0, self.x[2] - z0
+            unw[0] += dy - Ly * np.round(dy / Ly)
+            unw[1] += dz - Lz * np.round(dz / Lz)
+        return unw
 
     def conservative(self):
         return forces(self.x, self.Delta, self.p, self.method)

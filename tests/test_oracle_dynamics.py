@@ -141,7 +141,7 @@ def test_ideal_gas_equipartition_and_sheared_moments():
     n = sim.n
     L = sim.p.box[1]
     sim.run(400)
-    sxy, cxx, cyy, prof_c, prof_u = [], [], [], np.zeros(10), np.zeros(10)
+    sxy, cxx, cyy, prof_c, prof_u, prof_k = [], [], [], np.zeros(10), np.zeros(10), np.zeros(10)
     for _ in range(120):
         s = sim.run(40, sample_every=40)
         sxy.append(s[0, 3])
@@ -151,6 +151,7 @@ def test_ideal_gas_equipartition_and_sheared_moments():
         ob = O.observables(sim.x, sim.u, sim.Delta, sim.p, nbins=10)
         prof_c += ob["count"]
         prof_u += ob["sum_ux"]
+        prof_k += ob["sum_mc2"]
     rho = n / L ** 3
     assert np.mean(cyy) == pytest.approx(kT, rel=0.04)
     assert np.mean(cxx) == pytest.approx(kT * (1 + sr ** 2 / (2 * gamma ** 2)), rel=0.05)
@@ -160,6 +161,9 @@ def test_ideal_gas_equipartition_and_sheared_moments():
     slope = np.polyfit(centres, vx, 1)[0]
     assert slope == pytest.approx(sr, rel=0.05)
     assert prof_c.min() > 0.8 * prof_c.mean()
+    # temperature profile: flat, at the sum of the three stationary moments
+    mc2 = prof_k / prof_c
+    assert np.all(np.abs(mc2 / (kT * (3 + sr ** 2 / (2 * gamma ** 2))) - 1) < 0.06)
 
 
 def test_ideal_gas_no_shear_equipartition():

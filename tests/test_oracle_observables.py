@@ -1,0 +1,83 @@
+"""Pins of the oracle's remaining observables (Figs. profile and msd):
+
+* mean squared displacement along the gradient (y) and vorticity (z) axes
+  from unwrapped coordinates: exact ballistic growth of free particles that
+  cross the sheared faces many times, and the Ornstein-Uhlenbeck form of
+  Langevin particles;
+* the per-bin kinetic sums add up to the kinetic temperature, and the
+  centre-of-mass velocity is that of the in-box images.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2109_11083_amd import inputs
+
+
+def _gas(shear_rate, gamma, kT=1.0, n=400, L=5.0, seed=3, dt=0.01):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, L, size=(3, n))
+    c = inputs.maxwell(n, kT, 1.0, seed + 1)
+    u = inputs.streaming_initial_velocity(x, c, shear_rate, L)
+    p = O.make_params(n, (L, L, L), shear_rate=shear_rate, gamma=gamma, kT=kT, eps=0.0, rc=0.5,
+                      seed=seed, dt=dt)
+    return O.Sim(x, u, p)
+
+
+@pytest.mark.parametrize("shear_rate", [0.0, 0.7])
+def test_msd_free_flight_is_ballistic(shear_rate):
+    """gamma = 0 and no pair force: u_y and u_z never change (the velocity jump
+    at a sheared face acts on u_x only), so after n steps every particle has
+    moved by n dt u along y and z, through several faces."""
+    sim = _gas(shear_rate, 0.0)
+    ref = sim.x[1:].copy()
+    uyz = sim.u[1:].copy()
+    unw = sim.run_tracked(600, ref.copy())
+    t = 600 * sim.p.dt
+    assert np.abs(uyz).max() * t > 3 * sim.p.box[1]  # the fastest crossed several faces
+    assert np.allclose(unw - ref, t * uyz, rtol=0, atol=1e-9)
+    m = O.msd(unw, ref)
+    assert m == pytest.approx(((t * uyz) ** 2).mean(axis=1), rel=1e-10)
+    assert np.array_equal(sim.u[1:], uyz)
+
+
+@pytest.mark.slow
+def test_msd_langevin_ornstein_uhlenbeck():
+    """Per component, MSD(t) = 2 kT / (m gamma^2) (gamma t - 1 + exp(-gamma t))
+    for a Langevin particle started from equilibrium; under shear the y and z
+    components are unchanged (the friction couples c_x to c_y only)."""
+    gamma, kT = 2.0, 1.0
+    for sr in (0.0, 0.8):
+        sim = _gas(sr, gamma, kT=kT, n=600, dt=0.005)
+        ref = sim.x[1:].copy()
+        unw = ref.copy()
+        for k, nsteps in enumerate((100, 300, 600)):
+            unw = sim.run_tracked(nsteps - (0 if k == 0 else (100, 300, 600)[k - 1]), unw)
+            t = nsteps * sim.p.dt
+            want = 2 * kT / gamma ** 2 * (gamma * t - 1 + math.exp(-gamma * t))
+            m = O.msd(unw, ref)
+            assert m[0] == pytest.approx(want, rel=0.12), (sr, t)
+            assert m[1] == pytest.approx(want, rel=0.12), (sr, t)
+
+
+def test_observables_sums_and_in_box_velocity():
+    sim = _gas(0.9, 1.0)
+    sim.run(50)
+    p = sim.p
+    ob = O.observables(sim.x, sim.u, sim.Delta, p, nbins=7)
+    assert ob["count"].sum() == sim.n
+    assert ob["sum_mc2"].sum() / (3 * sim.n - 3) == pytest.approx(ob["kT"], rel=1e-13)
+    assert ob["sum_ux"].sum() / sim.n == pytest.approx(ob["com"][0], rel=1e-12, abs=1e-14)
+    # the same particles, one of them moved up by one box (and its velocity
+    # not yet jumped): every observable is unchanged
+    x, u = sim.x.copy(), sim.u.copy()
+    x[1, 0] += p.box[1]
+    x[0, 0] += sim.Delta
+    u[0, 0] += p.shear_rate * p.box[1]
+    ob2 = O.observables(x, u, sim.Delta, p, nbins=7)
+    assert np.array_equal(ob2["count"], ob["count"])
+    assert np.allclose(ob2["sum_ux"], ob["sum_ux"], rtol=0, atol=1e-12)
+    assert np.allclose(ob2["sum_mc2"], ob["sum_mc2"], rtol=1e-12)
+    assert np.allclose(ob2["com"], ob["com"], rtol=0, atol=1e-14)
