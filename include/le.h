@@ -173,16 +173,34 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
  * Eq. viscosity is <sigma_xy> / shear_rate.  sigma6: device float64[6]. */
 le_status le_stress(le_sim* s, double* sigma6);
 
-/* Observables of the current state (Fig. profile; Section 3): the particle
- * count and the summed lab flow velocity u_x in nbins equal bins along the
- * gradient axis y (each particle counted at its image inside the box, with
- * the velocity of that image), the kinetic temperature sum_i m c_i^2 / (3n-3)
- * of the peculiar velocities (Eq. vi), and the centre-of-mass lab velocity.
- * out: device float64[2*nbins + 4] = count[nbins], sum_ux[nbins], kT, com[3].
+/* Observables of the current state (Fig. profile; Section 3): per bin of
+ * nbins equal bins along the gradient axis y, the particle count, the summed
+ * lab flow velocity u_x and the summed peculiar kinetic term m c^2 (Eq. vi;
+ * the temperature profile is sum_mc2 / (3 count)), each particle counted at
+ * its image inside the box with the velocity of that image; then the kinetic
+ * temperature sum_i m c_i^2 / (3n-3) and the centre-of-mass lab velocity of
+ * the in-box images.
+ * out: device float64[3*nbins + 4] = count[nbins], sum_ux[nbins],
+ * sum_mc2[nbins], kT, com[3].
  * 1 <= nbins <= LE_MAX_BINS.  Sums are taken in a fixed order (reproducible).
  * Does not change the state. */
 #define LE_MAX_BINS 256
 le_status le_observables(le_sim* s, int32_t nbins, double* out);
+
+/* Unwrapped gradient and vorticity coordinates (for the mean squared
+ * displacement of Fig. msd): yz_out, device float64 [2][n] by tag, receives
+ * y + k_y L_y and z + k_z L_z, where k counts the periodic wraps the library
+ * has applied to the particle since le_init (the coordinates given to
+ * le_init are the origin, so a run restarted from le_get_state counts from
+ * the wrapped state).  The flow coordinate has no unwrapped form under the
+ * sheared boundary and is not reported.  Does not change the state. */
+le_status le_unwrapped(le_sim* s, double* yz_out);
+
+/* Mean squared displacement along y and z relative to ref_yz (device float64
+ * [2][n] by tag, from an earlier le_unwrapped of the same simulation):
+ * out2 (device float64[2]) = mean over particles of (y - y_ref)^2 and of
+ * (z - z_ref)^2 with unwrapped y, z.  Fixed summation order. */
+le_status le_msd(le_sim* s, const double* ref_yz, double* out2);
 
 /* Copy the current state out in tag order: positions x, lab velocities u and
  * the total force f of the current step (device float64 [3][n] each; any may

@@ -34,7 +34,7 @@ EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
     "le_timing_enable", "le_timing_read", "le_observables", "le_graph_create", "le_graph_launch",
-    "le_graph_destroy",
+    "le_graph_destroy", "le_unwrapped", "le_msd",
 ]
 LE_MAX_BINS = 256
 
@@ -109,6 +109,8 @@ def lib() -> C.CDLL:
     L.le_graph_create.argtypes = [vp, i64, i32, vp, i64, sim_pp]
     L.le_graph_launch.argtypes = [vp]
     L.le_graph_destroy.argtypes = [vp]
+    L.le_unwrapped.argtypes = [vp, vp]
+    L.le_msd.argtypes = [vp, vp, vp]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -195,6 +197,14 @@ def le_philox(ctr: int, key: int, out: int, count: int, stream: int | None) -> N
 
 def le_observables(sim: int, nbins: int, out: int) -> None:
     check(lib().le_observables(sim, nbins, out), "le_observables")
+
+
+def le_unwrapped(sim: int, yz_out: int) -> None:
+    check(lib().le_unwrapped(sim, yz_out), "le_unwrapped")
+
+
+def le_msd(sim: int, ref_yz: int, out2: int) -> None:
+    check(lib().le_msd(sim, ref_yz, out2), "le_msd")
 
 
 def le_graph_create(sim: int, nsteps: int, sample_every: int = 0, stress_ring: int | None = None,

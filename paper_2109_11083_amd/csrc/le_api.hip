@@ -150,7 +150,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.tile_nstage = (int32_t*)take((size_t)g.nblocks * sizeof(int32_t));
   t.bond = (p->chain_len > 0) ? (int32_t*)take(2 * np * sizeof(int32_t)) : nullptr;
   t.partials = (double*)take((size_t)g.nblocks * kStressComps * sizeof(double));
-  t.obs_part = (double*)take((size_t)((p->n + kBlock - 1) / kBlock) * (2 * LE_MAX_BINS + 4) *
+  t.obs_part = (double*)take((size_t)((p->n + kBlock - 1) / kBlock) * (3 * LE_MAX_BINS + 4) *
                              sizeof(double));
   unsigned long long* counter = (unsigned long long*)take(sizeof(unsigned long long));
   double* scratch6 = (double*)take(6 * sizeof(double));
@@ -473,6 +473,18 @@ le_status le_observables(le_sim* s, int32_t nbins, double* out) {
   if (!s || !out || nbins < 1 || nbins > LE_MAX_BINS) return LE_E_ARG;
   if (s->host_status) return s->host_status;
   return hip_check(launch_observables(s->d, s->stream, nbins, out));
+}
+
+le_status le_unwrapped(le_sim* s, double* yz_out) {
+  if (!s || !yz_out) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  return hip_check(launch_unwrapped(s->d, s->stream, yz_out));
+}
+
+le_status le_msd(le_sim* s, const double* ref_yz, double* out2) {
+  if (!s || !ref_yz || !out2) return LE_E_ARG;
+  if (s->host_status) return s->host_status;
+  return hip_check(launch_msd(s->d, s->stream, ref_yz, out2));
 }
 
 le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step) {

@@ -84,7 +84,7 @@ struct Dev {
   int32_t thermostat;              // LE_THERMO_*
   int32_t nblocks;                 // blocks of the pair kernels (= ntiles)
   // buffers (device)
-  double* pos[2];                  // double4 [np] each (x, y, z, unused)
+  double* pos[2];                  // double4 [np] each (x, y, z, wrap counts along y and z)
   double* vel[2];                  // [3][np]
   double* frc[2];                  // [3][np] total force of the current step
   int32_t* tag[2];                 // slot -> tag
@@ -115,7 +115,7 @@ struct Dev {
   int32_t ntiles;
   int32_t* bond;                   // [2][np] slot of the chain neighbour below/above, -1 if none
   double* partials;                // [nblocks][kStressComps] (nblocks = ntiles)
-  double* obs_part;                // [ceil(n / kBlock)][2 * LE_MAX_BINS + 4] observable partials
+  double* obs_part;                // [ceil(n / kBlock)][3 * LE_MAX_BINS + 4] observable partials
   Ctrl* ctrl;                      // current control copy (see Ctrl)
   // running max of |c|^2 of the last drift (bits of doubles >= 0) in kSlots
   // words of kLineU64 stride; two arrays alternate with the control copies
@@ -152,6 +152,8 @@ hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample
                         double* sample_out, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_stress_final(const Dev& d, hipStream_t s, double* out6, bool virial_only);
 hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* out);
+hipError_t launch_unwrapped(const Dev& d, hipStream_t s, double* out);
+hipError_t launch_msd(const Dev& d, hipStream_t s, const double* ref, double* out2);
 hipError_t launch_ctrl_copy(const Ctrl* src, Ctrl* dst, const unsigned long long* vsrc,
                             unsigned long long* vdst, hipStream_t s);
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,

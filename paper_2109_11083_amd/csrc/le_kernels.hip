@@ -45,6 +45,20 @@ __device__ __forceinline__ double wrap1(double& x, double L) {
   return k;
 }
 
+// The fourth word of each position holds the particle's wrap counts along y
+// and z since le_init (two int32 in the bits of the double; only ever copied,
+// never used in arithmetic).
+__device__ __forceinline__ void img_get(double w, int& ky, int& kz) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(w);
+  ky = (int)(uint32_t)(b >> 32);
+  kz = (int)(uint32_t)(b & 0xffffffffull);
+}
+__device__ __forceinline__ double img_put(int ky, int kz) {
+  const unsigned long long b = ((unsigned long long)(uint32_t)ky << 32) | (unsigned long long)(uint32_t)kz;
+  return __longlong_as_double((long long)b);
+}
+
+
 __device__ __forceinline__ int cell_index(double v, double inv, int n) {
   int k = (int)(v * inv);
   if (k < 0) k = 0;
@@ -225,7 +239,10 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
     x = x - ky * Delta;
     ux = ux - ky * d.sv;
     wrap1(x, d.Lx);
-    wrap1(z, d.Lz);
+    double kz = wrap1(z, d.Lz);
+    int cy, cz;
+    img_get(p.w, cy, cz);
+    p.w = img_put(cy + (int)ky, cz + (int)kz);
     double uy = U[np + i], uz = U[2 * np + i];
     if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
       latch(d.flags, LE_E_NONFINITE);
@@ -1356,32 +1373,36 @@ __global__ void k_ctrl_copy(const Ctrl* __restrict__ src, Ctrl* __restrict__ dst
 // lab u_x), then one thread per bin sums the block's particles of that bin in
 // index order; kinetic and centre-of-mass sums by wave shuffles.  The final
 // kernel adds the block partials in block order.
+constexpr int kObsStride = 3 * LE_MAX_BINS + 4;
+
 __global__ void __launch_bounds__(kBlock) k_obs_partial(Dev d, int nbins) {
   __shared__ int sbin[kBlock];
-  __shared__ double sux[kBlock];
+  __shared__ double sux[kBlock], smc[kBlock];
   __shared__ double red[kBlock / 64][4];
   if (d.flags->status) return;
   const Ctrl* c = d.ctrl;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int np = d.np;
   int b = -1;
-  double ux = 0.0, v[4] = {0.0, 0.0, 0.0, 0.0};
+  double ux = 0.0, mc2 = 0.0, v[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < d.n) {
     const double4 p = reinterpret_cast<const double4*>(d.pos[c->pos_cur])[i];
     const double* U = d.vel[c->aux_cur];
     const double u0 = U[i], u1 = U[np + i], u2 = U[2 * np + i];
     double y = p.y;
     const double ky = wrap1(y, d.Ly);
-    ux = u0 - ky * d.sv;
+    ux = u0 - ky * d.sv;  // lab velocity of the in-box image
     b = (int)(y / d.Ly * (double)nbins);
     if (b < 0) b = 0;
     if (b > nbins - 1) b = nbins - 1;
     const double cx = u0 - d.shear_rate * (p.y - 0.5 * d.Ly);
-    v[0] = d.mass * (cx * cx + u1 * u1 + u2 * u2);
-    v[1] = u0; v[2] = u1; v[3] = u2;
+    mc2 = d.mass * (cx * cx + u1 * u1 + u2 * u2);
+    v[0] = mc2;
+    v[1] = ux; v[2] = u1; v[3] = u2;
   }
   sbin[threadIdx.x] = b;
   sux[threadIdx.x] = ux;
+  smc[threadIdx.x] = mc2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -1390,31 +1411,98 @@ __global__ void __launch_bounds__(kBlock) k_obs_partial(Dev d, int nbins) {
     if (lane == 0) red[wid][k] = t;
   }
   __syncthreads();
-  const int stride = 2 * LE_MAX_BINS + 4;
-  double* out = d.obs_part + (size_t)blockIdx.x * stride;
+  double* out = d.obs_part + (size_t)blockIdx.x * kObsStride;
   for (int bb = threadIdx.x; bb < nbins; bb += kBlock) {
-    double cnt = 0.0, sum = 0.0;
+    double cnt = 0.0, sum = 0.0, sk = 0.0;
     for (int q = 0; q < kBlock; ++q)
-      if (sbin[q] == bb) { cnt += 1.0; sum += sux[q]; }
+      if (sbin[q] == bb) { cnt += 1.0; sum += sux[q]; sk += smc[q]; }
     out[bb] = cnt;
     out[nbins + bb] = sum;
+    out[2 * nbins + bb] = sk;
   }
   if (threadIdx.x < 4) {
     double t = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
-    out[2 * nbins + threadIdx.x] = t;
+    out[3 * nbins + threadIdx.x] = t;
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_obs_final(Dev d, int nbins, int nblk, double* out) {
   if (d.flags->status) return;
-  const int stride = 2 * LE_MAX_BINS + 4;
-  for (int k = threadIdx.x; k < 2 * nbins + 4; k += kBlock) {
+  for (int k = threadIdx.x; k < 3 * nbins + 4; k += kBlock) {
     double t = 0.0;
-    for (int b = 0; b < nblk; ++b) t += d.obs_part[(size_t)b * stride + k];
-    if (k == 2 * nbins) t = t / (3.0 * (double)d.n - 3.0);
-    else if (k > 2 * nbins) t = t / (double)d.n;
+    for (int b = 0; b < nblk; ++b) t += d.obs_part[(size_t)b * kObsStride + k];
+    if (k == 3 * nbins) t = t / (3.0 * (double)d.n - 3.0);
+    else if (k > 3 * nbins) t = t / (double)d.n;
     out[k] = t;
+  }
+}
+
+// Unwrapped y, z of every particle (slot order in, tag order out).
+__global__ void __launch_bounds__(kBlock) k_unwrapped(Dev d, double* __restrict__ out) {
+  if (d.flags->status) return;
+  const Ctrl* c = d.ctrl;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.n) return;
+  const double4 p = reinterpret_cast<const double4*>(d.pos[c->pos_cur])[i];
+  int ky, kz;
+  img_get(p.w, ky, kz);
+  const int t = d.tag[c->aux_cur][i];
+  out[t] = p.y + (double)ky * d.Ly;
+  out[d.n + t] = p.z + (double)kz * d.Lz;
+}
+
+// Mean squared y, z displacement against ref (tag order): block partials in
+// obs_part, then one block sums them in block order.
+__global__ void __launch_bounds__(kBlock) k_msd_partial(Dev d, const double* __restrict__ ref) {
+  __shared__ double red[kBlock / 64][2];
+  if (d.flags->status) return;
+  const Ctrl* c = d.ctrl;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (i < d.n) {
+    const double4 p = reinterpret_cast<const double4*>(d.pos[c->pos_cur])[i];
+    int ky, kz;
+    img_get(p.w, ky, kz);
+    const int t = d.tag[c->aux_cur][i];
+    const double dy = (p.y + (double)ky * d.Ly) - ref[t];
+    const double dz = (p.z + (double)kz * d.Lz) - ref[d.n + t];
+    v[0] = dy * dy;
+    v[1] = dz * dz;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < 2; ++k) {
+    double t = v[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
+    d.obs_part[(size_t)blockIdx.x * kObsStride + threadIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_msd_final(Dev d, int nblk, double* out2) {
+  __shared__ double red[kBlock / 64][2];
+  if (d.flags->status) return;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    v[0] += d.obs_part[(size_t)b * kObsStride];
+    v[1] += d.obs_part[(size_t)b * kObsStride + 1];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < 2; ++k) {
+    double t = v[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
+    out2[threadIdx.x] = t / (double)d.n;
   }
 }
 
@@ -1589,6 +1677,16 @@ hipError_t launch_observables(const Dev& d, hipStream_t s, int nbins, double* ou
   const int nblk = blocks_for(d.n);
   hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kBlock), 0, s, d, nbins);
   hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kBlock), 0, s, d, nbins, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_unwrapped(const Dev& d, hipStream_t s, double* out) {
+  hipLaunchKernelGGL(k_unwrapped, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, out);
+  return hipGetLastError();
+}
+hipError_t launch_msd(const Dev& d, hipStream_t s, const double* ref, double* out2) {
+  const int nblk = blocks_for(d.n);
+  hipLaunchKernelGGL(k_msd_partial, dim3(nblk), dim3(kBlock), 0, s, d, ref);
+  hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kBlock), 0, s, d, nblk, out2);
   return hipGetLastError();
 }
 hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, int32_t* cell_of,

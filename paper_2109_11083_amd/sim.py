@@ -165,16 +165,35 @@ class Sim:
         return s.cpu().numpy()
 
     def observables(self, nbins: int = 50, out: torch.Tensor | None = None, host: bool = True):
-        """y-profiles of count and summed u_x, kinetic kT and CoM velocity of the current state."""
+        """y-profiles of count, summed u_x and summed m c^2, kinetic kT and CoM
+        velocity of the current state."""
         if out is None:
-            out = torch.empty(2 * nbins + 4, dtype=torch.float64, device=self.device)
+            out = torch.empty(3 * nbins + 4, dtype=torch.float64, device=self.device)
         B.le_observables(self.handle, nbins, out.data_ptr())
         if not host:
             return out
         self.sync()
         o = out.cpu().numpy()
-        return dict(count=o[:nbins], sum_ux=o[nbins:2 * nbins], kT=float(o[2 * nbins]),
-                    com=o[2 * nbins + 1:2 * nbins + 4])
+        return dict(count=o[:nbins], sum_ux=o[nbins:2 * nbins], sum_mc2=o[2 * nbins:3 * nbins],
+                    kT=float(o[3 * nbins]), com=o[3 * nbins + 1:3 * nbins + 4])
+
+    def unwrapped(self, host: bool = True):
+        """Unwrapped y and z of every particle ([2][n] by tag)."""
+        out = torch.empty((2, self.params.n), dtype=torch.float64, device=self.device)
+        B.le_unwrapped(self.handle, out.data_ptr())
+        if not host:
+            return out
+        self.sync()
+        return out.cpu().numpy()
+
+    def msd(self, ref: torch.Tensor):
+        """Mean squared y and z displacement against ref (a device tensor from
+        unwrapped(host=False))."""
+        assert ref.is_cuda and ref.dtype == torch.float64 and ref.shape == (2, self.params.n)
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        B.le_msd(self.handle, ref.data_ptr(), out.data_ptr())
+        self.sync()
+        return out.cpu().numpy()
 
     def state(self):
         n = self.params.n

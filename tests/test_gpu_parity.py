@@ -284,6 +284,7 @@ def _check_observables(got, ref, tag):
     assert np.array_equal(got["count"], ref["count"]), tag
     scale = max(np.abs(ref["sum_ux"]).max(), 1.0)
     assert np.abs(got["sum_ux"] - ref["sum_ux"]).max() / scale < 1e-12, tag
+    assert np.abs(got["sum_mc2"] - ref["sum_mc2"]).max() / ref["sum_mc2"].max() < 1e-12, tag
     assert abs(got["kT"] - ref["kT"]) / ref["kT"] < 1e-12, tag
     assert np.abs(got["com"] - ref["com"]).max() < 1e-12 * max(1.0, np.abs(ref["com"]).max() * 1e3), tag
 
@@ -301,6 +302,56 @@ def test_observables_mid_run(nbins):
     ref = O.observables(x, u, 0.0, _oracle_params(p), nbins=nbins)
     assert got["count"].sum() == p.n
     _check_observables(got, ref, nbins)
+    sim.close()
+
+
+def test_observables_along_a_run_with_pending_crossings():
+    """Observables every few steps of a sheared run with a skin, so that many
+    particles have crossed a face without being wrapped yet, against the oracle
+    run beside it (trajectories agree to ~1e-9, hence the looser bounds)."""
+    w, p = _lj_case(shear_rate=0.8, skin=0.4)
+    sim = Sim(p, w.x, w.u, step0=0)
+    ref = O.Sim(w.x, w.u, _oracle_params(p), step0=0)
+    for k in range(6):
+        sim.step(7)
+        ref.run(7)
+        got = sim.observables(20)
+        want = O.observables(ref.x, ref.u, ref.Delta, ref.p, nbins=20)
+        assert np.array_equal(got["count"], want["count"]), k
+        assert np.abs(got["sum_ux"] - want["sum_ux"]).max() < 1e-6, k
+        assert np.abs(got["sum_mc2"] - want["sum_mc2"]).max() < 1e-6, k
+        assert abs(got["kT"] - want["kT"]) < 1e-9, k
+        assert np.abs(got["com"] - want["com"]).max() < 1e-9, k
+    assert sim.stats()["rebuilds"] < 40
+    sim.close()
+
+
+def test_msd_matches_oracle():
+    """Unwrapped y, z and their mean squared displacement over a sheared run
+    in a small box (many face crossings) against the oracle's unwrapped
+    coordinates, accumulated from per-step minimum-image increments."""
+    w, p = _lj_case(n_side=8, shear_rate=1.0, skin=0.3, kT=2.0)
+    p.dt = 0.01
+    sim = Sim(p, w.x, w.u, step0=0)
+    ref = O.Sim(w.x, w.u, _oracle_params(p), step0=0)
+    r_gpu = sim.unwrapped(host=False)
+    r0 = sim.unwrapped()
+    # the origin of the wrap counts is the input
+    assert np.abs(r0 - np.asarray(w.x)[1:]).max() < 1e-12
+    unw = ref.x[1:].copy()
+    r_ref = unw.copy()
+    for k in range(4):
+        sim.step(25)
+        unw = ref.run_tracked(25, unw)
+        m_gpu = sim.msd(r_gpu)
+        m_ref = O.msd(unw, r_ref)
+        g = sim.unwrapped()
+        dg = g - r0
+        dr = unw - r_ref
+        assert np.abs(dg - dr).max() < 1e-8, k
+        assert np.allclose(m_gpu, m_ref, rtol=1e-7), (k, m_gpu, m_ref)
+    outside = (unw[0] < 0) | (unw[0] >= p.box[1])
+    assert outside.sum() >= 5  # particles that crossed a sheared face
     sim.close()
 
 
