@@ -488,32 +488,56 @@ double orc_dpd_theta(uint64_t seed, int64_t step, int64_t ti, int64_t tj)
 /*   F_i += [-gamma w^2 (e . v_ij) + sqrt(24 gamma kT / dt) w theta_ij] e,     */
 /*   F_j -= the same.                                                          */
 /* The total force is F^c plus these pair terms only (no per-particle drag). */
-static void thermostat_dpd(int64_t n, const double *x, const double *u, const double *Fc,
-                           double *F, int64_t step, double Delta, const orc_params *p)
+/* The pairs come from the brute-force loop (method 0) or the grid of O6     */
+/* (method 1), which visit the same pair set.                                */
+typedef struct {
+    int64_t n, step;
+    const double *x, *u;
+    double *F;
+    double Delta, sv, pref;
+    const orc_params *p;
+} dpd_ctx;
+
+static void dpd_pair_cb(void *ctx, int64_t i, int64_t j, const double d_in[3], double r2_in)
 {
-    const double sv = p->shear_rate * p->box[1];
-    const double rd2 = p->dpd_rc * p->dpd_rc;
-    const double pref = sqrt(24.0 * p->gamma * p->kT / p->dt);
-    for (int64_t k = 0; k < 3 * n; ++k) F[k] = Fc[k];
+    dpd_ctx *c = (dpd_ctx *)ctx;
+    const int64_t n = c->n;
+    const double *u = c->u;
     double d[3];
     int32_t img[3];
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t j = i + 1; j < n; ++j) {
-            double r2 = orc_disp(x, n, i, j, Delta, p->box, d, img);
-            if (!(r2 < rd2)) continue;
-            double r = sqrt(r2);
-            double e[3] = {d[0] / r, d[1] / r, d[2] / r};
-            double v[3] = {(u[i] - u[j]) - (double)img[1] * sv, u[n + i] - u[n + j],
-                           u[2 * n + i] - u[2 * n + j]};
-            double w = 1.0 - r / p->dpd_rc;
-            double ev = e[0] * v[0] + e[1] * v[1];
-            ev = ev + e[2] * v[2];
-            double f = -p->gamma * w * w * ev + pref * w * orc_dpd_theta(p->seed, step, i, j);
-            for (int a = 0; a < 3; ++a) {
-                F[a * n + i] += f * e[a];
-                F[a * n + j] -= f * e[a];
+    double r2 = orc_disp(c->x, n, i, j, c->Delta, c->p->box, d, img);
+    (void)d_in; (void)r2_in;
+    double r = sqrt(r2);
+    double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+    double v[3] = {(u[i] - u[j]) - (double)img[1] * c->sv, u[n + i] - u[n + j],
+                   u[2 * n + i] - u[2 * n + j]};
+    double w = 1.0 - r / c->p->dpd_rc;
+    double ev = e[0] * v[0] + e[1] * v[1];
+    ev = ev + e[2] * v[2];
+    double f = -c->p->gamma * w * w * ev + c->pref * w * orc_dpd_theta(c->p->seed, c->step, i, j);
+    for (int a = 0; a < 3; ++a) {
+        c->F[a * n + i] += f * e[a];
+        c->F[a * n + j] -= f * e[a];
+    }
+}
+
+static void thermostat_dpd(int64_t n, const double *x, const double *u, const double *Fc,
+                           double *F, int64_t step, double Delta, const orc_params *p, int method)
+{
+    dpd_ctx c = {n, step, x, u, F, Delta, p->shear_rate * p->box[1],
+                 sqrt(24.0 * p->gamma * p->kT / p->dt), p};
+    const double rd2 = p->dpd_rc * p->dpd_rc;
+    for (int64_t k = 0; k < 3 * n; ++k) F[k] = Fc[k];
+    if (method == 0) {
+        double d[3];
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double r2 = orc_disp(x, n, i, j, Delta, p->box, d, NULL);
+                if (r2 < rd2) dpd_pair_cb(&c, i, j, d, r2);
             }
-        }
+    } else {
+        grid_pairs(n, x, Delta, p->box, p->dpd_rc, dpd_pair_cb, &c);
+    }
 }
 
 /* Eq. langevin with the friction acting on the peculiar velocity           */
@@ -579,7 +603,7 @@ int orc_step(int64_t n, double *x, double *u, double *F, int64_t *step, const or
     double *Fc = Fc_out ? Fc_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, W6, NULL);
     if (rc != ORC_OK) { if (!Fc_out) free(Fc); return rc; }
-    if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, s, Delta, p);
+    if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, s, Delta, p, method);
     else thermostat(n, x, u, Fc, F, s, p);
     for (int64_t k = 0; k < 3 * n; ++k) u[k] = u[k] + h * F[k];
     for (int64_t k = 0; k < 3 * n; ++k)
@@ -599,7 +623,7 @@ int orc_init(int64_t n, double *x, double *u, double *F, int64_t step0, const or
     double *Fc = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, NULL, NULL);
     if (rc == ORC_OK) {
-        if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, step0, Delta, p);
+        if (p->thermostat == 1) thermostat_dpd(n, x, u, Fc, F, step0, Delta, p, method);
         else thermostat(n, x, u, Fc, F, step0, p);
     }
     free(Fc);
