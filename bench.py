@@ -42,12 +42,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def lj_params(n, shear_rate, precision, seed=21, skin=0.3):
+# friction per thermostat on the LJ fluid (the paper's xi = 1 Langevin, xi_DPD = 5)
+LJ_GAMMA = {"langevin": 1.0, "langevin_abs": 1.0, "dpd": 5.0}
+DPD_PAIR_FLOPS = 30.0         # DPD dissipative + random pair terms (Philox is integer work)
+
+
+def lj_params(n, shear_rate, precision, seed=21, skin=0.3, thermostat="langevin"):
     from paper_2109_11083_amd import inputs
     from paper_2109_11083_amd.sim import Params
     w = inputs.lj_workload(n=n, shear_rate=shear_rate, seed=seed)
     p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, skin=skin,
-               precision=precision, rc=2.5, dt=0.005, kT=1.0, gamma=1.0)
+               precision=precision, rc=2.5, dt=0.005, kT=1.0, gamma=LJ_GAMMA[thermostat],
+               thermostat=thermostat)
     return w, p
 
 
@@ -66,19 +72,19 @@ def kg_params(shear_rate, precision, seed=31, skin=0.3, n_chains=KG_CHAINS, chai
     return w, p
 
 
-def pick_skin(n, shear_rate, precision, workload):
+def pick_skin(n, shear_rate, precision, workload, thermostat="langevin"):
     """Autotuned skin for a workload (short bursts; see paper_2109_11083_amd.tune)."""
     from paper_2109_11083_amd.tune import autotune
     if workload == "kg":
         w, p = kg_params(shear_rate, precision)
     else:
-        w, p = lj_params(n, shear_rate, precision)
+        w, p = lj_params(n, shear_rate, precision, thermostat=thermostat)
     best, table = autotune(p, w.x, w.u)
     return best.skin, [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
 
 
 def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIMING_FORCE, skin=0.3,
-            workload="lj"):
+            workload="lj", thermostat="langevin"):
     """One timed run.  timing: le_timing_enable mask for HIP-event timing inside the
     timed region (bit 0: the plain-step force kernel; 0xF: every phase; bits 8..: stride)."""
     import torch
@@ -87,7 +93,7 @@ def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIM
     if workload == "kg":
         w, p = kg_params(shear_rate, precision, skin=skin)
     else:
-        w, p = lj_params(n, shear_rate, precision, skin=skin)
+        w, p = lj_params(n, shear_rate, precision, skin=skin, thermostat=thermostat)
     sim = Sim(p, w.x, w.u, step0=0)
     ring = torch.zeros((max(steps // sample_every, 1), 6), dtype=torch.float64, device="cuda")
     if warmup > 0:
@@ -159,12 +165,12 @@ def serving_bench(count=64):
     return out
 
 
-def cpu_baseline(n, shear_rate, nsteps):
+def cpu_baseline(n, shear_rate, nsteps, thermostat="langevin"):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
-    w, p = lj_params(n, shear_rate, "fp64")
+    w, p = lj_params(n, shear_rate, "fp64", thermostat=thermostat)
     op = O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma,
-                       rc=p.rc, seed=p.seed)
+                       rc=p.rc, seed=p.seed, thermostat=thermostat)
     sim = O.Sim(w.x, w.u, op, step0=0, method=1)
     t0 = time.perf_counter()
     sim.run(nsteps)
@@ -219,6 +225,9 @@ def main():
                     help="neighbour-list skin, or 'auto' (autotuned per workload, short bursts)")
     ap.add_argument("--workload", default="lj", choices=["lj", "kg"],
                     help="lj: 256,000-particle LJ fluid (the headline); kg: 2000 x 200 Kremer-Grest melt")
+    ap.add_argument("--thermostat", default="langevin", choices=["langevin", "dpd", "langevin_abs"],
+                    help="LJ workload: Langevin on the peculiar velocity (gamma 1), DPD (gamma 5) or "
+                         "Langevin on the lab velocity (gamma 1)")
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
                     help="shear-rate sweep serving: p50/p99 time-to-result and sweep throughput")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -239,8 +248,10 @@ def main():
     sr = args.shear_rate if args.shear_rate is not None else (0.01 if kg else 0.1)
 
     tune_table = None
+    th = "langevin" if kg else args.thermostat
+    dpd = th == "dpd"
     if args.skin == "auto":
-        skin, tune_table = pick_skin(args.n, sr, args.precision, args.workload)
+        skin, tune_table = pick_skin(args.n, sr, args.precision, args.workload, thermostat=th)
         log(f"bench: autotuned skin {skin}: {tune_table}")
     else:
         skin = float(args.skin)
@@ -249,7 +260,8 @@ def main():
     log(f"bench: {args.workload} {size} shear_rate={sr} {args.precision} "
         f"steps={args.steps} warmup={args.warmup} skin={skin}")
     r = run_gpu(args.n, sr, args.precision, args.steps, args.warmup,
-                timing=0 if args.no_timing else TIMING_FORCE, skin=args.skin, workload=args.workload)
+                timing=0 if args.no_timing else TIMING_FORCE, skin=args.skin, workload=args.workload,
+                thermostat=th)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
 
@@ -258,7 +270,7 @@ def main():
     # every 8th launch of the timed region
     force_ms, force_n = r["phases"]["force"]
     roofline = None
-    kname = ("k_force_kg400k_" if kg else "k_force_lj256k_") + args.precision
+    kname = ("k_force_kg400k_" if kg else ("k_force_dpd_lj256k_" if dpd else "k_force_lj256k_")) + args.precision
     if force_n > 0:
         avg_s = force_ms / 1e3 / force_n
         traffic = read_traffic(kname + "_traffic")
@@ -271,22 +283,24 @@ def main():
         else:
             rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
             pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
-            flops_pp = PAIR_FLOPS * pairs_pp / 2.0 + STEP_FLOPS
+            flops_pp = (PAIR_FLOPS + (DPD_PAIR_FLOPS if dpd else 0.0)) * pairs_pp / 2.0 + STEP_FLOPS
             achieved = r["n"] * flops_pp / avg_s / 1e12
             roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS,
                             unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=traffic,
                             flops_per_particle=round(flops_pp, 1))
-        roofline.update(kernel="k_force (fused pair force + Langevin + velocity Verlet), plain steps",
+        roofline.update(kernel=("k_force<kDpdForce> (LJ + DPD pair terms; the kicks and drift follow in "
+                                "k_integrate), plain steps") if dpd else
+                        "k_force (fused pair force + Langevin + velocity Verlet), plain steps",
                         avg_kernel_us=round(avg_s * 1e6, 3), launches=force_n,
                         hbm_GBs_if_traffic=(round(traffic / avg_s / 1e9, 1) if traffic else None))
 
     extra = {}
     # per-phase device time of the same workload (all phases event-timed; a separate, shorter run)
     b = run_gpu(args.n, sr, args.precision, min(args.steps, 2000), 100, timing=0xF, skin=args.skin,
-                workload=args.workload)
+                workload=args.workload, thermostat=th)
     extra["phase_us_per_step"] = {k: round(1e3 * v[0] / b["steps"], 2) for k, v in b["phases"].items()}
     log(f"bench: phases {extra['phase_us_per_step']}")
-    if not args.no_extra:
+    if not args.no_extra and not dpd:
         if not kg:
             for sr2 in (0.01, 1.0):
                 e = run_gpu(args.n, sr2, args.precision, 2000, 100, skin=args.skin)
@@ -315,12 +329,12 @@ def main():
                                         skin=kskin)
             log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
 
-    if args.serve and not kg:
+    if args.serve and not kg and th == "langevin":
         extra["serving"] = serving_bench(args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline and not kg:
-        cpu = cpu_baseline(args.n, sr, args.cpu_steps)
+        cpu = cpu_baseline(args.n, sr, args.cpu_steps, thermostat=th)
         log(f"bench: cpu oracle {cpu['value']:.4e} particle-steps/s")
 
     if kg:
@@ -328,8 +342,11 @@ def main():
               f"WCA + FENE(30, 1.5), T=1, Langevin gamma=0.5 on peculiar velocity, shear_rate={sr}, "
               f"dt=0.01, skin {args.skin}, {args.precision}; overlap-free lattice-path start")
     else:
+        tdesc = {"langevin": "Langevin gamma=1 on peculiar velocity",
+                 "langevin_abs": "Langevin gamma=1 on lab velocity",
+                 "dpd": "DPD gamma=5, r_c 2.5"}[th]
         wl = (f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
-              f"T=1, Langevin gamma=1 on peculiar velocity, shear_rate={sr}, "
+              f"T=1, {tdesc}, shear_rate={sr}, "
               f"dt=0.005, skin {args.skin}, {args.precision}")
     out = {
         "metric": METRIC,
