@@ -134,6 +134,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     t.frc[b] = (double*)take(3 * np * sizeof(double));
     t.tag[b] = (int32_t*)take(np * sizeof(int32_t));
   }
+  t.vt = (p->thermostat == LE_THERMO_DPD) ? (double*)take(4 * np * sizeof(double)) : nullptr;
   t.slot_of_tag = (int32_t*)take(np * sizeof(int32_t));
   t.cell_of = (int32_t*)take(np * sizeof(int32_t));
   t.rank = (int32_t*)take(np * sizeof(int32_t));
@@ -163,6 +164,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     for (int b = 0; b < 2; ++b) {
       d->pos[b] = t.pos[b]; d->vel[b] = t.vel[b]; d->frc[b] = t.frc[b]; d->tag[b] = t.tag[b];
     }
+    d->vt = t.vt;
     d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->bucket = t.bucket;
     d->cell_count = t.cell_count; d->cell_start = t.cell_start;
     d->nl16 = t.nl16; d->nlo = t.nlo; d->nlc = t.nlc;

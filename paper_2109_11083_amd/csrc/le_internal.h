@@ -87,6 +87,8 @@ struct Dev {
   double* pos[2];                  // double4 [np] each (x, y, z, wrap counts along y and z)
   double* vel[2];                  // [3][np]
   double* frc[2];                  // [3][np] total force of the current step
+  double* vt;                      // DPD only: double4 [np] (u_x, u_y, u_z, tag) of the current slots,
+                                   // packed before each force evaluation (one gather per partner)
   int32_t* tag[2];                 // slot -> tag
   int32_t* slot_of_tag;            // tag -> slot
   int32_t* cell_of;                // cell of each slot (binning pass)

@@ -1092,7 +1092,7 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
   double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double4 pi = valid ? pi_ld : make_double4(0.0, 0.0, 0.0, 0.0);
   const uint32_t st_lo = (uint32_t)(uint64_t)c->step, st_hi = (uint32_t)((uint64_t)c->step >> 32);
-  const int* __restrict__ Tg = d.tag[ac];
+  const double4* __restrict__ VT = reinterpret_cast<const double4*>(d.vt);
   if (valid) {
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
     // staged partners (already shifted to their image): the particle's two
@@ -1150,17 +1150,11 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       double4 pj[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) pj[u] = P[sl[u]];
-      // DPD: the partners' tags and velocities (the sentinel's are never used)
-      int tj[DPD ? 8 : 1];
-      double vj[DPD ? 24 : 1];
+      // DPD: the partners' velocities and tags, one 32-byte gather each
+      double4 vj[DPD ? 8 : 1];
       if (DPD) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          tj[u] = Tg[sl[u]];
-          vj[3 * u] = Uv[sl[u]];
-          vj[3 * u + 1] = Uv[np + sl[u]];
-          vj[3 * u + 2] = Uv[2 * np + sl[u]];
-        }
+        for (int u = 0; u < 8; ++u) vj[u] = VT[sl[u]];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1175,8 +1169,8 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
         add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
         if (DPD) {
           // the image s_y boxes up streams faster by s_y gamma_dot L_y
-          const double vx = (u0_ld - vj[3 * u]) - (double)sy * d.sv;
-          dpd_pair(d, st_lo, st_hi, tag_ld, tj[u], vx, u1_ld - vj[3 * u + 1], u2_ld - vj[3 * u + 2],
+          const double vx = (u0_ld - vj[u].x) - (double)sy * d.sv;
+          dpd_pair(d, st_lo, st_hi, tag_ld, (int)vj[u].w, vx, u1_ld - vj[u].y, u2_ld - vj[u].z,
                    dx, dy, dz, r2, gx, gy, gz);
         }
       }
@@ -1295,6 +1289,22 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.5 * w[k]; }
     block_partials(vals, d.partials, lb);
   }
+}
+
+// DPD: pack the current velocities and tags of every slot (and zeros for the
+// sentinel slot n) into vt, so that the force kernel gathers one 32-byte
+// record per partner.
+__global__ void __launch_bounds__(kBlock) k_pack_vt(Dev d) {
+  if (d.flags->status) return;
+  const Ctrl* c = d.ctrl;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int np = d.np;
+  double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (i < d.n) {
+    const double* U = d.vel[c->aux_cur];
+    v = make_double4(U[i], U[np + i], U[2 * np + i], (double)d.tag[c->aux_cur][i]);
+  }
+  if (i <= d.n) reinterpret_cast<double4*>(d.vt)[i] = v;
 }
 
 // DPD steps, after k_force<kDpdForce>: u += dt/(2m) F (the step's second
@@ -1644,7 +1654,8 @@ hipError_t launch_force(const Dev& d, hipStream_t s, ForceMode mode, bool sample
       else launch_force_t<kStepFused, false>(d, s, f_out, nullptr, e0, e1);
       break;
     case kDpdForce:
-      if (d.staged) return hipErrorInvalidValue;  // DPD partners come from global memory
+      if (d.staged || !d.vt) return hipErrorInvalidValue;  // DPD partners come from global memory
+      hipLaunchKernelGGL(k_pack_vt, dim3(blocks_for(d.n + 1)), dim3(kBlock), 0, s, d);
       if (sample) launch_force_s<kDpdForce, true, false>(d, s, f_out, sample_out, e0, e1);
       else launch_force_s<kDpdForce, false, false>(d, s, f_out, nullptr, e0, e1);
       break;
