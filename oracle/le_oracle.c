@@ -37,6 +37,9 @@ typedef struct {
     int64_t n_chains;
     int32_t chain_len;  /* 0 => no bonds */
     int32_t thermostat; /* 0 Langevin on the peculiar velocity, 1 DPD, 2 Langevin on the lab velocity */
+    int32_t velocity;   /* 0: u is the lab velocity; 1: u is the peculiar velocity (Eq. vi), the */
+                        /* streaming velocity enters the drift only (Section 2.2)               */
+    int32_t pad_;
 } orc_params;
 
 enum { ORC_OK = 0, ORC_E_BOND = -4, ORC_E_NONFINITE = -5, ORC_E_ARG = -1 };
@@ -544,13 +547,14 @@ static void thermostat_dpd(int64_t n, const double *x, const double *u, const do
 /* c = u - shear_rate (y - L_y/2) e_x (Eqs. shear-rate, vi): the total force  */
 /* on one particle is F^c - gamma m c + sqrt(24 gamma m kT / dt) theta.       */
 /* Thermostat 2 applies the friction to the lab velocity u instead (the      */
-/* paper's xi_abs, Section 3.2), which drags the flow profile.               */
+/* paper's xi_abs, Section 3.2), which drags the flow profile.  With         */
+/* peculiar storage u already is c.                                          */
 static void thermostat(int64_t n, const double *x, const double *u, const double *Fc,
                        double *F, int64_t step, const orc_params *p)
 {
     const double Ly = p->box[1];
     const double pref = sqrt(24.0 * p->gamma * p->mass * p->kT / p->dt);
-    const double sr = p->thermostat == 2 ? 0.0 : p->shear_rate;
+    const double sr = (p->thermostat == 2 || p->velocity == 1) ? 0.0 : p->shear_rate;
     for (int64_t i = 0; i < n; ++i) {
         double c[3];
         c[0] = u[i] - sr * (x[n + i] - 0.5 * Ly);
@@ -572,8 +576,9 @@ void orc_stress(int64_t n, const double *x, const double *u, const double *W6,
     const double Ly = p->box[1];
     const double V = p->box[0] * p->box[1] * p->box[2];
     double K[6] = {0, 0, 0, 0, 0, 0};
+    const double csr = p->velocity == 1 ? 0.0 : p->shear_rate;
     for (int64_t i = 0; i < n; ++i) {
-        double cx = u[i] - p->shear_rate * (x[n + i] - 0.5 * Ly);
+        double cx = u[i] - csr * (x[n + i] - 0.5 * Ly);
         double cy = u[n + i], cz = u[2 * n + i];
         K[0] += p->mass * cx * cx; K[1] += p->mass * cy * cy; K[2] += p->mass * cz * cz;
         K[3] += p->mass * cx * cy; K[4] += p->mass * cx * cz; K[5] += p->mass * cy * cz;
@@ -596,10 +601,19 @@ int orc_step(int64_t n, double *x, double *u, double *F, int64_t *step, const or
 {
     const double h = 0.5 * p->dt / p->mass;
     for (int64_t k = 0; k < 3 * n; ++k) u[k] = u[k] + h * F[k];
-    for (int64_t k = 0; k < 3 * n; ++k) x[k] = x[k] + p->dt * u[k];
+    if (p->velocity == 1) {
+        /* peculiar storage: x moves with u_x plus the streaming velocity at */
+        /* the particle's height before the drift                            */
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = x[i] + p->dt * (u[i] + p->shear_rate * (x[n + i] - 0.5 * p->box[1]));
+        for (int64_t k = n; k < 3 * n; ++k) x[k] = x[k] + p->dt * u[k];
+    } else {
+        for (int64_t k = 0; k < 3 * n; ++k) x[k] = x[k] + p->dt * u[k];
+    }
     int64_t s = *step + 1;
     double Delta = orc_offset(s, p->dt, p->shear_rate, p->box[0], p->box[1]);
-    orc_le_wrap(n, x, u, Delta, p);
+    /* a peculiar velocity is continuous across the sheared faces: no jump */
+    orc_le_wrap(n, x, p->velocity == 1 ? NULL : u, Delta, p);
     double *Fc = Fc_out ? Fc_out : (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, W6, NULL);
     if (rc != ORC_OK) { if (!Fc_out) free(Fc); return rc; }
@@ -619,7 +633,7 @@ int orc_init(int64_t n, double *x, double *u, double *F, int64_t step0, const or
              int method)
 {
     double Delta = orc_offset(step0, p->dt, p->shear_rate, p->box[0], p->box[1]);
-    orc_le_wrap(n, x, u, Delta, p);
+    orc_le_wrap(n, x, p->velocity == 1 ? NULL : u, Delta, p);
     double *Fc = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     int rc = orc_forces(n, x, Delta, p, method, Fc, NULL, NULL);
     if (rc == ORC_OK) {
@@ -670,13 +684,14 @@ void orc_observables(int64_t n, const double *x, const double *u, double Delta, 
     for (int64_t i = 0; i < n; ++i) {
         double y = x[n + i];
         double ky = orc_wrap(&y, Ly);
-        double ux = u[i] - ky * sv;
+        /* lab u_x of the in-box image */
+        double ux = p->velocity == 1 ? u[i] + p->shear_rate * (y - 0.5 * Ly) : u[i] - ky * sv;
         int32_t b = (int32_t)(y / Ly * (double)nbins);
         if (b < 0) b = 0;
         if (b > nbins - 1) b = nbins - 1;
         count[b] += 1.0;
         sum_ux[b] += ux;
-        double cx = u[i] - p->shear_rate * (x[n + i] - 0.5 * Ly);
+        double cx = p->velocity == 1 ? u[i] : u[i] - p->shear_rate * (x[n + i] - 0.5 * Ly);
         double mc2 = p->mass * (cx * cx + u[n + i] * u[n + i] + u[2 * n + i] * u[2 * n + i]);
         sum_mc2[b] += mc2;
         k2 += mc2;

@@ -49,9 +49,12 @@ class Params(C.Structure):
         ("n_chains", C.c_int64),
         ("chain_len", C.c_int32),
         ("thermostat", C.c_int32),
+        ("velocity", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 THERMOSTATS = {"langevin": 0, "dpd": 1, "langevin_abs": 2}
+VELOCITIES = {"lab": 0, "peculiar": 1}
 
 
 _lib = None
@@ -127,7 +130,7 @@ class OracleError(RuntimeError):
 
 def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, pair="lj",
                 eps=1.0, sigma=1.0, rc=2.5, fene_k=30.0, fene_r0=1.5, lj_shift=0.0,
-                seed=1, chain_len=0, n_chains=0, thermostat="langevin", dpd_rc=0.0,
+                seed=1, chain_len=0, n_chains=0, thermostat="langevin", dpd_rc=0.0, velocity="lab",
                 **_ignored) -> Params:
     p = Params()
     for a in range(3):
@@ -143,6 +146,7 @@ def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, p
     p.n_chains = n_chains
     p.thermostat = THERMOSTATS[thermostat] if isinstance(thermostat, str) else int(thermostat)
     p.dpd_rc = dpd_rc if dpd_rc > 0 else rc
+    p.velocity = VELOCITIES[velocity] if isinstance(velocity, str) else int(velocity)
     return p
 
 
