@@ -91,6 +91,16 @@ typedef int32_t le_status;
 #define LE_THERMO_LANGEVIN_LAB 2 /* Eq. langevin with the friction on the lab velocity u (the
                                 paper's xi_abs, Section 3.2): F_i += -gamma m u_i + noise       */
 
+/* Velocity storage (Section 2.2, Eq. vi).  The velocity arrays given to
+ * le_init and returned by le_get_state are the stored velocities.          */
+#define LE_VEL_LAB 0      /* u is the lab velocity; a particle crossing a sheared face has its
+                             u_x changed by -/+ gamma_dot L_y; x moves with u              */
+#define LE_VEL_PECULIAR 1 /* u is the peculiar velocity c of Eq. vi (continuous across the
+                             faces); x moves with c_x + gamma_dot (y - L_y/2), the streaming
+                             velocity of its height.  Drops the -gamma_dot c_y coupling of the
+                             lab form (a different dynamics, as integrated in ESPResSo++).
+                             Requires LE_THERMO_LANGEVIN (friction on c).                  */
+
 /* Parameters of one simulation (Sections 2.1, 2.2, 2.4).  All 8-byte fields
  * come first so that the layout has no padding. */
 typedef struct le_params {
@@ -120,7 +130,7 @@ typedef struct le_params {
                           in an LDS halo per tile, 2 = partners read from global memory;
                           the physics is the same (sums may differ in the last bits) */
   int32_t thermostat;  /* LE_THERMO_*: how gamma and kT act (Section 2.2)                */
-  int32_t reserved;    /* must be 0                                                      */
+  int32_t velocity;    /* LE_VEL_*: what the stored (and exchanged) velocities are       */
 } le_params;
 
 /* Device bytes needed for a simulation with these parameters.  Pure host

@@ -29,6 +29,8 @@ LE_MIXED = 1
 LE_THERMO_LANGEVIN = 0
 LE_THERMO_DPD = 1
 LE_THERMO_LANGEVIN_LAB = 2
+LE_VEL_LAB = 0
+LE_VEL_PECULIAR = 1
 
 EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
@@ -65,7 +67,7 @@ class le_params(C.Structure):
         ("max_neighbors", C.c_int32),
         ("tune", C.c_int32),
         ("thermostat", C.c_int32),
-        ("reserved", C.c_int32),
+        ("velocity", C.c_int32),
     ]
 
 

@@ -65,7 +65,9 @@ le_status validate(const le_params* p, Geometry* g) {
   if (p->precision != LE_FP64 && p->precision != LE_MIXED) return LE_E_ARG;
   if (p->tune < 0 || p->tune > 2) return LE_E_ARG;
   if (p->thermostat < LE_THERMO_LANGEVIN || p->thermostat > LE_THERMO_LANGEVIN_LAB) return LE_E_ARG;
-  if (p->reserved != 0) return LE_E_ARG;
+  if (p->velocity != LE_VEL_LAB && p->velocity != LE_VEL_PECULIAR) return LE_E_ARG;
+  // peculiar storage is defined with the Langevin force on the stored velocity
+  if (p->velocity == LE_VEL_PECULIAR && p->thermostat != LE_THERMO_LANGEVIN) return LE_E_ARG;
   double rc = p->rc;
   if (rc <= 0.0) rc = (p->pair == LE_PAIR_WCA) ? pow(2.0, 1.0 / 6.0) * p->sigma : 2.5 * p->sigma;
   if (p->thermostat == LE_THERMO_DPD) {
@@ -188,6 +190,10 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->lx = p->box[0] / (double)g.nc[0];
   d->shear_rate = p->shear_rate;
   d->sv = p->shear_rate * p->box[1];
+  const bool pec = p->velocity == LE_VEL_PECULIAR;
+  d->c_sr = pec ? 0.0 : p->shear_rate;
+  d->drift_sr = pec ? p->shear_rate : 0.0;
+  d->jump_sv = pec ? 0.0 : d->sv;
   d->dt = p->dt;
   d->h = 0.5 * p->dt / p->mass;
   d->gamma_m = p->gamma * p->mass;

@@ -57,6 +57,11 @@ struct Dev {
   double inv_lx, inv_ly, inv_lz;   // cells per unit length (n_a / L_a)
   double lx;                       // cell length along x
   double shear_rate, sv;           // gamma_dot and gamma_dot * L_y
+  // velocity storage (LE_VEL_*): the peculiar velocity is c = u - c_sr (y - L_y/2) e_x,
+  // the drift moves x by dt (u_x + drift_sr (y - L_y/2)), a face crossing jumps
+  // u_x by -k_y jump_sv.  Lab storage: (gamma_dot, 0, gamma_dot L_y); peculiar
+  // storage: (0, gamma_dot, 0).
+  double c_sr, drift_sr, jump_sv;
   double dt, h;                    // time step and dt / (2 m)
   double gamma_m;                  // gamma * m
   double pref;                     // sqrt(24 gamma m kT / dt)

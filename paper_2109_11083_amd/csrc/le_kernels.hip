@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
     const double Delta = sc.Delta;
     double ky = wrap1(y, d.Ly);
     x = x - ky * Delta;
-    ux = ux - ky * d.sv;
+    ux = ux - ky * d.jump_sv;  // velocity jump (lab storage only)
     wrap1(x, d.Lx);
     double kz = wrap1(z, d.Lz);
     int cy, cz;
@@ -885,11 +885,11 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     double ux = U[i] + d.h * F[i];
     double uy = U[np + i] + d.h * F[np + i];
     double uz = U[2 * np + i] + d.h * F[2 * np + i];
-    double cx = ux - d.shear_rate * (p.y - 0.5 * d.Ly);
+    double cx = ux - d.c_sr * (p.y - 0.5 * d.Ly);
     v2 = cx * cx + uy * uy + uz * uz;
     U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
     double4 q;
-    q.x = p.x + d.dt * ux;
+    q.x = p.x + d.dt * (ux + d.drift_sr * (p.y - 0.5 * d.Ly));
     q.y = p.y + d.dt * uy;
     q.z = p.z + d.dt * uz;
     q.w = p.w;
@@ -1228,7 +1228,7 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       if (f_out) {
         f_out[t] = fx; f_out[d.n + t] = fy; f_out[2 * d.n + t] = fz;
       }
-      double cx = u0_ld - d.shear_rate * (pi.y - 0.5 * d.Ly);
+      double cx = u0_ld - d.c_sr * (pi.y - 0.5 * d.Ly);
       double cy = u1_ld, cz = u2_ld;
       double m = d.mass;
       kin[0] = m * cx * cx; kin[1] = m * cy * cy; kin[2] = m * cz * cz;
@@ -1249,7 +1249,7 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     // inside the box (positions are wrapped lazily, so a particle above the
     // top face still carries the velocity it had before crossing)
     double cx = d.thermostat == LE_THERMO_LANGEVIN_LAB ? ux - d.sv * floor(pi.y / d.Ly)
-                                                       : ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
+                                                       : ux - d.c_sr * (pi.y - 0.5 * d.Ly);
     double Fx = (fx - d.gamma_m * cx) + d.pref * u01c(ctr[0]);
     double Fy = (fy - d.gamma_m * uy) + d.pref * u01c(ctr[1]);
     double Fz = (fz - d.gamma_m * uz) + d.pref * u01c(ctr[2]);
@@ -1260,7 +1260,7 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       ux = ux + d.h * Fx; uy = uy + d.h * Fy; uz = uz + d.h * Fz;
       if (SAMPLE) {
         double m = d.mass;
-        double cxn = ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
+        double cxn = ux - d.c_sr * (pi.y - 0.5 * d.Ly);
         kin[0] = m * cxn * cxn; kin[1] = m * uy * uy; kin[2] = m * uz * uz;
         kin[3] = m * cxn * uy; kin[4] = m * cxn * uz; kin[5] = m * uy * uz;
       }
@@ -1269,10 +1269,10 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
         F[i] = Fx; F[np + i] = Fy; F[2 * np + i] = Fz;
       } else {
         ux = ux + d.h * Fx; uy = uy + d.h * Fy; uz = uz + d.h * Fz;
-        double cxh = ux - d.shear_rate * (pi.y - 0.5 * d.Ly);
+        double cxh = ux - d.c_sr * (pi.y - 0.5 * d.Ly);
         v2 = cxh * cxh + uy * uy + uz * uz;
         double4 q;
-        q.x = pi.x + d.dt * ux;
+        q.x = pi.x + d.dt * (ux + d.drift_sr * (pi.y - 0.5 * d.Ly));
         q.y = pi.y + d.dt * uy;
         q.z = pi.z + d.dt * uz;
         q.w = pi.w;
@@ -1334,16 +1334,16 @@ __global__ void __launch_bounds__(kTile) k_integrate(Dev d) {
     double uz = U[2 * np + i] + d.h * Fz;
     if (SAMPLE) {
       const double m = d.mass;
-      const double cx = ux - d.shear_rate * (p.y - 0.5 * d.Ly);
+      const double cx = ux - d.c_sr * (p.y - 0.5 * d.Ly);
       kin[0] = m * cx * cx; kin[1] = m * uy * uy; kin[2] = m * uz * uz;
       kin[3] = m * cx * uy; kin[4] = m * cx * uz; kin[5] = m * uy * uz;
     }
     if (!LAST) {
       ux = ux + d.h * Fx; uy = uy + d.h * Fy; uz = uz + d.h * Fz;
-      const double cxh = ux - d.shear_rate * (p.y - 0.5 * d.Ly);
+      const double cxh = ux - d.c_sr * (p.y - 0.5 * d.Ly);
       v2 = cxh * cxh + uy * uy + uz * uz;
       double4 q;
-      q.x = p.x + d.dt * ux;
+      q.x = p.x + d.dt * (ux + d.drift_sr * (p.y - 0.5 * d.Ly));
       q.y = p.y + d.dt * uy;
       q.z = p.z + d.dt * uz;
       q.w = p.w;
@@ -1402,11 +1402,11 @@ __global__ void __launch_bounds__(kBlock) k_obs_partial(Dev d, int nbins) {
     const double u0 = U[i], u1 = U[np + i], u2 = U[2 * np + i];
     double y = p.y;
     const double ky = wrap1(y, d.Ly);
-    ux = u0 - ky * d.sv;  // lab velocity of the in-box image
+    ux = (u0 - ky * d.jump_sv) + d.drift_sr * (y - 0.5 * d.Ly);  // lab u_x of the in-box image
     b = (int)(y / d.Ly * (double)nbins);
     if (b < 0) b = 0;
     if (b > nbins - 1) b = nbins - 1;
-    const double cx = u0 - d.shear_rate * (p.y - 0.5 * d.Ly);
+    const double cx = u0 - d.c_sr * (p.y - 0.5 * d.Ly);
     mc2 = d.mass * (cx * cx + u1 * u1 + u2 * u2);
     v[0] = mc2;
     v[1] = ux; v[2] = u1; v[3] = u2;

@@ -17,6 +17,7 @@ PAIRS = {"lj": B.LE_PAIR_LJ, "wca": B.LE_PAIR_WCA}
 PRECISIONS = {"fp64": B.LE_FP64, "mixed": B.LE_MIXED}
 THERMOSTATS = {"langevin": B.LE_THERMO_LANGEVIN, "dpd": B.LE_THERMO_DPD,
                "langevin_abs": B.LE_THERMO_LANGEVIN_LAB}
+VELOCITIES = {"lab": B.LE_VEL_LAB, "peculiar": B.LE_VEL_PECULIAR}
 
 
 @dataclass
@@ -45,6 +46,7 @@ class Params:
     tune: int = 0
     thermostat: str = "langevin"
     dpd_rc: float = 0.0
+    velocity: str = "lab"
 
     def to_c(self) -> B.le_params:
         p = B.le_params()
@@ -64,6 +66,7 @@ class Params:
         p.tune = int(self.tune)
         p.thermostat = THERMOSTATS[self.thermostat]
         p.dpd_rc = float(self.dpd_rc)
+        p.velocity = VELOCITIES[self.velocity]
         return p
 
     @property

@@ -72,7 +72,7 @@ def test_workspace_bytes_and_geometry_errors():
             B.le_workspace_bytes(_lj(tune=t).to_c())
         assert e.value.code == B.LE_E_ARG
     # thermostats: unknown code, DPD with the LDS halo layout or a weight
-    # cutoff beyond the pair cutoff, a non-zero reserved word
+    # cutoff beyond the pair cutoff, an unknown velocity storage
     for bad in (dict(thermostat="dpd", tune=1), dict(thermostat="dpd", dpd_rc=2.6)):
         with pytest.raises(B.LeError) as e:
             B.le_workspace_bytes(_lj(**bad).to_c())
@@ -84,12 +84,16 @@ def test_workspace_bytes_and_geometry_errors():
             B.le_workspace_bytes(c)
         assert e.value.code == B.LE_E_ARG
     c = _lj().to_c()
-    c.reserved = 1
+    c.velocity = 2
     with pytest.raises(B.LeError) as e:
         B.le_workspace_bytes(c)
     assert e.value.code == B.LE_E_ARG
+    for th in ("dpd", "langevin_abs"):  # peculiar storage takes the Langevin force on c only
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(_lj(velocity="peculiar", thermostat=th).to_c())
+        assert e.value.code == B.LE_E_ARG
     for ok in (dict(thermostat="dpd"), dict(thermostat="dpd", dpd_rc=1.0, tune=2),
-               dict(thermostat="langevin_abs", tune=1)):
+               dict(thermostat="langevin_abs", tune=1), dict(velocity="peculiar")):
         assert B.le_workspace_bytes(_lj(**ok).to_c()) > 0
 
 

@@ -1,5 +1,6 @@
-"""GPU parity of the DPD thermostat and of the Langevin friction on the lab
-velocity (Section 2.2; xi_DPD and xi_abs of Section 3.2) against the oracle.
+"""GPU parity of the DPD thermostat, of the Langevin friction on the lab
+velocity (Section 2.2; xi_DPD and xi_abs of Section 3.2) and of the
+peculiar-velocity storage (Section 2.2) against the oracle.
 
 DPD pair sums are accumulated in list order on the GPU and in (i, j) order in
 the oracle, so forces agree to rounding (1e-12 relative to the force scale)
@@ -32,7 +33,8 @@ def _log(msg):
 def _oracle_params(p: Params):
     return O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma, mass=p.mass,
                          eps=p.eps, sigma=p.sigma, rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
-                         chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc)
+                         chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc,
+                         velocity=p.velocity)
 
 
 def e_F(F, Fref):
@@ -190,4 +192,55 @@ def test_lab_langevin_lj_trajectory_lazy_wrap():
     assert np.abs(dx).max() < 1e-8
     sg = ring.cpu().numpy()
     assert np.abs(sg - sref).max() / np.abs(sref[:, :3]).max() < 1e-9
+    sim.close()
+
+
+def test_peculiar_storage_ideal_gas_bitwise_skin0():
+    """Stored peculiar velocities, streaming velocity in the drift only, no
+    jump at the faces: bit for bit with a rebuild every step."""
+    rng = np.random.default_rng(8)
+    n, L = 500, 9.0
+    x = rng.uniform(0, L, size=(3, n))
+    c = inputs.maxwell(n, 1.0, 1.0, 9)
+    p = Params(n=n, box=(L, L, L), shear_rate=0.9, eps=0.0, rc=1.0, skin=0.0, gamma=1.3, kT=1.1,
+               dt=0.01, seed=78, velocity="peculiar")
+    sim = Sim(p, x, c, step0=5)
+    ref = O.Sim(x, c, _oracle_params(p), step0=5)
+    for _ in range(3):
+        sim.step(50)
+        ref.run(50)
+        gx, gu, gf, st = sim.state()
+        assert st == ref.step
+        assert np.array_equal(gx, ref.x)
+        assert np.array_equal(gu, ref.u)
+        assert np.array_equal(gf, ref.F)
+    sim.close()
+
+
+@pytest.mark.parametrize("skin", [0.0, 0.3])
+def test_peculiar_storage_lj_trajectory(skin):
+    w = inputs.lj_workload(n_side=10, shear_rate=0.5, seed=12)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.5, seed=12, skin=skin, velocity="peculiar")
+    L = w.box[1]
+    c0 = np.asarray(w.u).copy()
+    c0[0] -= 0.5 * (np.asarray(w.x)[1] - L / 2)  # the input's peculiar velocities
+    sim = Sim(p, w.x, c0)
+    ref = O.Sim(w.x, c0, _oracle_params(p))
+    ring = sim.step(100, sample_every=10)
+    sref = ref.run(100, sample_every=10)
+    got = sim.observables(10)
+    want = O.observables(ref.x, ref.u, ref.Delta, ref.p, nbins=10)
+    gx, gu, gf, st = sim.state()
+    Lv = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - Lv * np.round(dx / Lv)
+    _log(f"peculiar storage skin={skin}: max|dx|={np.abs(dx).max():.3e} max|du|={np.abs(gu - ref.u).max():.3e}")
+    assert np.abs(dx).max() < 1e-8
+    assert np.abs(gu - ref.u).max() < 1e-7
+    sg = ring.cpu().numpy()
+    assert np.abs(sg - sref).max() / np.abs(sref[:, :3]).max() < 1e-9
+    assert np.array_equal(got["count"], want["count"])
+    assert np.abs(got["sum_ux"] - want["sum_ux"]).max() < 1e-6
+    assert np.abs(got["sum_mc2"] - want["sum_mc2"]).max() < 1e-6
+    assert np.abs(got["com"] - want["com"]).max() < 1e-9
     sim.close()
