@@ -32,6 +32,7 @@ typedef struct {
     double fene_k, fene_r0;
     double lj_shift;    /* energy shift added to every pair inside rc (energy only) */
     double dpd_rc;      /* DPD weight-function cutoff (thermostat 1) */
+    double angle_k;     /* cosine angle term k_a (Eq. angle); 0 = none */
     uint64_t seed;
     int64_t n;
     int64_t n_chains;
@@ -375,6 +376,56 @@ static int add_bonds(const double *x, double Delta, force_ctx *fc)
     return ORC_OK;
 }
 
+/* Cosine angle term of the KG chains (Eq. angle), read as the standard       */
+/* bending potential k_a (1 - cos(theta - theta_0)) with theta_0 = 180 deg,   */
+/* i.e. V = k_a (1 + cos theta), theta the angle at the middle bead j of       */
+/* consecutive beads (a, j, b) between b1 = x_a - x_j and b2 = x_b - x_j      */
+/* (Lees-Edwards nearest images): zero for a straight chain.  F = -grad V:    */
+/*   F_a = -k_a [b2 / (l1 l2) - cos(theta) b1 / l1^2],  F_b likewise,          */
+/*   F_j = -(F_a + F_b); virial of the angle b1 (x) F_a + b2 (x) F_b.           */
+static void angle_cos(const double b1[3], const double b2[3], double k, double Fa[3], double Fb[3],
+                      double *e)
+{
+    double l11 = b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2];
+    double l22 = b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2];
+    double l12 = sqrt(l11) * sqrt(l22);
+    double c = (b1[0] * b2[0] + b1[1] * b2[1] + b1[2] * b2[2]) / l12;
+    *e = k * (1.0 + c);
+    for (int a = 0; a < 3; ++a) {
+        Fa[a] = -k * (b2[a] / l12 - c * b1[a] / l11);
+        Fb[a] = -k * (b1[a] / l12 - c * b2[a] / l22);
+    }
+}
+
+static void add_angles(const double *x, double Delta, force_ctx *fc)
+{
+    const orc_params *p = fc->p;
+    const int64_t n = fc->n;
+    if (p->chain_len < 3 || p->angle_k == 0.0) return;
+    double b1[3], b2[3], Fa[3], Fb[3], e;
+    for (int64_t c = 0; c < p->n_chains; ++c)
+        for (int32_t k = 1; k + 1 < p->chain_len; ++k) {
+            int64_t j = c * p->chain_len + k, a = j - 1, b = j + 1;
+            orc_disp(x, n, a, j, Delta, p->box, b1, NULL);
+            orc_disp(x, n, b, j, Delta, p->box, b2, NULL);
+            angle_cos(b1, b2, p->angle_k, Fa, Fb, &e);
+            for (int q = 0; q < 3; ++q) {
+                fc->F[q * n + a] += Fa[q];
+                fc->F[q * n + b] += Fb[q];
+                fc->F[q * n + j] -= Fa[q] + Fb[q];
+            }
+            if (fc->W) {
+                fc->W[0] += b1[0] * Fa[0] + b2[0] * Fb[0];
+                fc->W[1] += b1[1] * Fa[1] + b2[1] * Fb[1];
+                fc->W[2] += b1[2] * Fa[2] + b2[2] * Fb[2];
+                fc->W[3] += b1[0] * Fa[1] + b2[0] * Fb[1];
+                fc->W[4] += b1[0] * Fa[2] + b2[0] * Fb[2];
+                fc->W[5] += b1[1] * Fa[2] + b2[1] * Fb[2];
+            }
+            if (fc->e) *fc->e += e;
+        }
+}
+
 /* Conservative forces (pairs + bonds) of a configuration, plus the virial   */
 /* W_ab = sum_{i<j} d_a F_ij,b and the potential energy.  method 0: all      */
 /* pairs by brute force; 1: through the grid of O6.  F, W6, energy may be    */
@@ -397,7 +448,9 @@ int orc_forces(int64_t n, const double *x, double Delta, const orc_params *p, in
     } else {
         grid_pairs(n, x, Delta, p->box, p->rc, lj_pair_cb, &fc);
     }
-    return add_bonds(x, Delta, &fc);
+    int rc = add_bonds(x, Delta, &fc);
+    if (rc == ORC_OK) add_angles(x, Delta, &fc);
+    return rc;
 }
 
 /* Conservative force on a few chosen particles, each summed over every other */
@@ -428,6 +481,20 @@ int orc_forces_sample(int64_t n, const double *x, double Delta, const orc_params
                 double f, e;
                 if (bond_fene(r2, p, &f, &e) != ORC_OK) return ORC_E_BOND;
                 for (int a = 0; a < 3; ++a) acc[a] += f * d[a];
+            }
+            /* angles centred at i - 1 (i is its second end), at i, and at */
+            /* i + 1 (i is its first end)                                   */
+            if (p->chain_len >= 3 && p->angle_k != 0.0) {
+                for (int64_t cj = i - 1; cj <= i + 1; ++cj) {
+                    int64_t kc = k + (cj - i);
+                    if (kc < 1 || kc + 1 >= p->chain_len) continue;
+                    double b1[3], b2[3], Fa[3], Fb[3], e;
+                    orc_disp(x, n, cj - 1, cj, Delta, p->box, b1, NULL);
+                    orc_disp(x, n, cj + 1, cj, Delta, p->box, b2, NULL);
+                    angle_cos(b1, b2, p->angle_k, Fa, Fb, &e);
+                    for (int a = 0; a < 3; ++a)
+                        acc[a] += (cj == i + 1) ? Fa[a] : (cj == i - 1) ? Fb[a] : -(Fa[a] + Fb[a]);
+                }
             }
         }
         for (int a = 0; a < 3; ++a) Fs[3 * s + a] = acc[a];
