@@ -6,10 +6,13 @@
  * ESPResSo++", arXiv 2109.11083.  One call advances a sheared periodic box
  * of N particles: Lees-Edwards cell build (Section 2.3, Fig. decomp),
  * LJ/WCA pair forces (Eqs. lj, lj-shift) and Kremer-Grest FENE bonds
- * (Eq. fene), velocity Verlet with the boundary crossing of Eq. pos_new, a
- * Langevin force on the peculiar velocity (Eqs. vi, langevin) driven by
+ * (Eq. fene) with an optional cosine angle term (Eq. angle), velocity
+ * Verlet with the boundary crossing of Eq. pos_new, a Langevin force on the
+ * peculiar velocity (Eqs. vi, langevin) or the paper's alternatives (DPD,
+ * Eqs. dissipative, random, omega; friction on the lab velocity) driven by
  * counter-based Philox4x32-10 noise, and the Irving-Kirkwood stress that
- * yields the viscosity (Eqs. tensor, viscosity).
+ * yields the viscosity (Eqs. tensor, viscosity), with profiles and mean
+ * squared displacements (Figs. profile, msd).
  *
  * Axes: x is the flow direction, y the gradient direction (the paper's z),
  * z the vorticity direction.  The periodic image directly above the box
@@ -118,6 +121,10 @@ typedef struct le_params {
   double fene_r0;      /* FENE maximal bond length R0                               */
   double dpd_rc;       /* cutoff r_c of the DPD weight omega (Eq. omega); 0 = rc;
                           must not exceed rc (the pair list covers rc only)      */
+  double angle_k;      /* cosine angle term of the chains (Eq. angle), read as
+                          V = angle_k (1 + cos theta) per consecutive bead triple,
+                          theta the angle at the middle bead (minimum at 180
+                          degrees; the paper's KG melts use 1.5); 0 = none, >= 0   */
   int64_t n_chains;    /* linear chains: tag = chain*chain_len + k; 0 = no bonds    */
   uint64_t seed;       /* Philox key of the thermostat noise                        */
   int32_t chain_len;   /* beads per chain (0 = no bonds)                            */

@@ -79,6 +79,7 @@ le_status validate(const le_params* p, Geometry* g) {
   if (p->n_chains > 0) {
     if (p->chain_len < 2 || p->n_chains * (int64_t)p->chain_len > p->n) return LE_E_ARG;
     if (!(p->fene_r0 > 0.0) || !(p->fene_k >= 0.0)) return LE_E_ARG;
+    if (!(p->angle_k >= 0.0) || !isfinite(p->angle_k)) return LE_E_ARG;
   }
   double rlist = rc + p->skin;
   for (int a = 0; a < 3; ++a) {
@@ -232,6 +233,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   }
   d->fene_k = p->fene_k;
   d->fene_r02 = p->fene_r0 * p->fene_r0;
+  d->angle_k = (p->n_chains > 0 && p->chain_len >= 3) ? p->angle_k : 0.0;
   d->inv_vol = 1.0 / (p->box[0] * p->box[1] * p->box[2]);
   d->n = (int32_t)p->n;
   d->np = (int32_t)g.np;

@@ -938,6 +938,38 @@ __device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, 
   }
 }
 
+// Lees-Edwards nearest-image displacement a - b (the integers by rounding;
+// valid for bonded beads, which are far closer than half a box).
+__device__ __forceinline__ void near_disp(const Dev& d, double4 a, double4 b, double Delta, double& dx,
+                                          double& dy, double& dz) {
+  const double dy0 = a.y - b.y;
+  const double sy = rint(dy0 / d.Ly);
+  dy = dy0 - sy * d.Ly;
+  const double dx0 = (a.x - b.x) - sy * Delta;
+  const double sx = rint(dx0 / d.Lx);
+  dx = dx0 - sx * d.Lx;
+  const double dz0 = a.z - b.z;
+  const double sz = rint(dz0 / d.Lz);
+  dz = dz0 - sz * d.Lz;
+}
+
+// Cosine angle term (Eq. angle) read as V = k (1 + cos theta), minimum at a
+// straight chain: theta the angle between b1 = x_a - x_j and b2 = x_b - x_j at
+// the middle bead j.  Forces on the two ends (F_j = -(F_a + F_b)):
+//   F_a = -k [b2 / (l1 l2) - cos(theta) b1 / l1^2],  F_b likewise.
+__device__ __forceinline__ void angle_cos(const double b1[3], const double b2[3], double k, double Fa[3],
+                                          double Fb[3]) {
+  const double l11 = b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2];
+  const double l22 = b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2];
+  const double l12 = sqrt(l11) * sqrt(l22);
+  const double c = (b1[0] * b2[0] + b1[1] * b2[1] + b1[2] * b2[2]) / l12;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fa[a] = -k * (b2[a] / l12 - c * b1[a] / l11);
+    Fb[a] = -k * (b1[a] / l12 - c * b2[a] / l22);
+  }
+}
+
 // DPD pair terms (Eqs. dissipative, random, omega) on particle i from one
 // partner: d = x_i - x_j(image), v = u_i - u_j(image) (the image's streaming
 // velocity already removed), r2 = |d|^2.  Adds f d with
@@ -1178,19 +1210,16 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     }
     if (BONDS && half == 0) {
       // FENE (Eq. fene), always float64; displacement by the nearest image
+      int jb[2];
+      double4 pb[2];
       for (int b = 0; b < 2; ++b) {
         int j = d.bond[b * np + i];
+        jb[b] = j;
         if (j < 0) continue;
         double4 pj = P[j];
-        double dy0 = pi.y - pj.y;
-        double sy = rint(dy0 / d.Ly);
-        double dy = dy0 - sy * d.Ly;
-        double dx0 = (pi.x - pj.x) - sy * Delta;
-        double sx = rint(dx0 / d.Lx);
-        double dx = dx0 - sx * d.Lx;
-        double dz0 = pi.z - pj.z;
-        double sz = rint(dz0 / d.Lz);
-        double dz = dz0 - sz * d.Lz;
+        pb[b] = pj;
+        double dx, dy, dz;
+        near_disp(d, pi, pj, Delta, dx, dy, dz);
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
         if (!(r2 < d.fene_r02)) {
@@ -1199,6 +1228,40 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
         }
         double f = -d.fene_k / (1.0 - r2 / d.fene_r02);
         add_pair<VIR>(f, dx, dy, dz, fx, fy, fz, w);
+      }
+      if (d.angle_k != 0.0) {
+        // cosine angle term (Eq. angle): the angles centred at i (its virial
+        // is counted here), at the bead below (i is its second end) and at
+        // the bead above (i is its first end)
+        double b1[3], b2[3], Fa[3], Fb[3];
+        if (jb[0] >= 0 && jb[1] >= 0) {
+          near_disp(d, pb[0], pi, Delta, b1[0], b1[1], b1[2]);
+          near_disp(d, pb[1], pi, Delta, b2[0], b2[1], b2[2]);
+          angle_cos(b1, b2, d.angle_k, Fa, Fb);
+          fx -= Fa[0] + Fb[0]; fy -= Fa[1] + Fb[1]; fz -= Fa[2] + Fb[2];
+          if (VIR) {
+            // w holds twice the virial (pairs and bonds are met from both
+            // ends), so the angle's single contribution enters doubled
+            w[0] += 2.0 * (b1[0] * Fa[0] + b2[0] * Fb[0]);
+            w[1] += 2.0 * (b1[1] * Fa[1] + b2[1] * Fb[1]);
+            w[2] += 2.0 * (b1[2] * Fa[2] + b2[2] * Fb[2]);
+            w[3] += 2.0 * (b1[0] * Fa[1] + b2[0] * Fb[1]);
+            w[4] += 2.0 * (b1[0] * Fa[2] + b2[0] * Fb[2]);
+            w[5] += 2.0 * (b1[1] * Fa[2] + b2[1] * Fb[2]);
+          }
+        }
+        for (int b = 0; b < 2; ++b) {
+          const int j = jb[b];
+          if (j < 0) continue;
+          const int j2 = d.bond[b * np + j];  // the next bead beyond j
+          if (j2 < 0) continue;
+          const double4 p2 = P[j2];
+          // angle (j2, j, i) below or (i, j, j2) above; i's force is that of its end
+          near_disp(d, p2, pb[b], Delta, b1[0], b1[1], b1[2]);
+          near_disp(d, pi, pb[b], Delta, b2[0], b2[1], b2[2]);
+          angle_cos(b1, b2, d.angle_k, Fa, Fb);
+          fx += Fb[0]; fy += Fb[1]; fz += Fb[2];
+        }
       }
     }
   }

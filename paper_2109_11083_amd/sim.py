@@ -47,6 +47,7 @@ class Params:
     thermostat: str = "langevin"
     dpd_rc: float = 0.0
     velocity: str = "lab"
+    angle_k: float = 0.0
 
     def to_c(self) -> B.le_params:
         p = B.le_params()
@@ -67,6 +68,7 @@ class Params:
         p.thermostat = THERMOSTATS[self.thermostat]
         p.dpd_rc = float(self.dpd_rc)
         p.velocity = VELOCITIES[self.velocity]
+        p.angle_k = float(self.angle_k)
         return p
 
     @property

@@ -35,7 +35,8 @@ def e_F(F, Fref):
 def _oracle_params(p: Params, **over):
     kw = dict(shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma, mass=p.mass, eps=p.eps,
               sigma=p.sigma, rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
-              chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc)
+              chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc,
+              velocity=p.velocity, angle_k=p.angle_k)
     kw.update(over)
     return O.make_params(p.n, p.box, **kw)
 
@@ -179,6 +180,31 @@ def test_forces_mixed_lj(frac, tune):
 def test_forces_fp64_kg_fene(tune):
     w, p = _kg_case(tune=tune)
     _forces_case(w.x, w.u, p, 777, 1e-12, 1e-12)
+
+
+@pytest.mark.parametrize("tune", [0, 1, 2])
+def test_forces_fp64_kg_angles(tune):
+    """KG chains with the cosine angle term: forces and virial (the angle's
+    virial counted once, at its middle bead) against the oracle."""
+    w, p = _kg_case(tune=tune, angle_k=1.5)
+    _forces_case(w.x, w.u, p, 4321, 1e-12, 1e-12)
+
+
+def test_kg_angles_trajectory():
+    w, p = _kg_case(angle_k=1.5, skin=0.4, shear_rate=0.05)
+    sim = Sim(p, w.x, w.u)
+    ref = O.Sim(w.x, w.u, _oracle_params(p))
+    ring = sim.step(60, sample_every=10)
+    sref = ref.run(60, sample_every=10)
+    gx, gu, gf, st = sim.state()
+    L = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - L * np.round(dx / L)
+    _log(f"kg angles trajectory max|dx|={np.abs(dx).max():.3e}")
+    assert np.abs(dx).max() < 1e-8
+    assert e_F(gf, ref.F) < 1e-7
+    assert np.abs(ring.cpu().numpy() - sref).max() / np.abs(sref[:, :3]).max() < 1e-9
+    sim.close()
 
 
 @pytest.mark.parametrize("tune", [0, 1])
