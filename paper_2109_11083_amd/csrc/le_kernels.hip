@@ -1159,22 +1159,31 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     // partners that were not staged: global memory, exact image arithmetic;
     // eight gathers in flight, the next eight indices requested ahead.  With
     // the halo each thread takes its own sub-list; without, one thread per
-    // particle takes both.
-    for (int sub = STAGED ? half : 0; sub < (STAGED ? half + 1 : 2); ++sub) {
-    const int vo = sub * np + i;
-    const int nbo = d.n_og[vo] / kOtherBatch;
+    // particle takes both as one sequence.
+    // the sub-lists this thread takes, read as one sequence of blocks of 4
+    // (sub-list s_lo, then s_hi) so that one prefetch pipeline runs across both
+    const int s_lo = STAGED ? half : 0, s_hi = STAGED ? half : 1;
+    const int nbo0 = d.n_og[s_lo * np + i] / kOtherBatch;
+    const int nbo = nbo0 + (s_hi != s_lo ? d.n_og[s_hi * np + i] / kOtherBatch : 0);
     const int last_ob = d.K / kOtherBatch - 1;
-    const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo) + vo;
-    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc) + vo;
-    uint4 jn0 = l4[0], jn1 = l4[(size_t)min(1, last_ob) * np2];
-    uint32_t cn0 = c4[0], cn1 = c4[(size_t)min(1, last_ob) * np2];
+    auto ooff = [&](int q) -> size_t {
+      const bool first = q < nbo0;
+      const int blk = min(first ? q : q - nbo0, last_ob);
+      return (size_t)blk * np2 + (size_t)(first ? s_lo : s_hi) * np + i;
+    };
+    const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo);
+    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc);
+    uint4 jn0 = l4[ooff(0)], jn1 = l4[ooff(1)];
+    uint32_t cn0 = c4[ooff(0)], cn1 = c4[ooff(1)];
+    {
     for (int b = 0; b < nbo; b += 2) {
       const uint4 j0 = jn0, j1 = jn1;
       const uint32_t c0 = cn0, c1 = cn1;
-      jn0 = l4[(size_t)min(b + 2, last_ob) * np2];
-      jn1 = l4[(size_t)min(b + 3, last_ob) * np2];
-      cn0 = c4[(size_t)min(b + 2, last_ob) * np2];
-      cn1 = c4[(size_t)min(b + 3, last_ob) * np2];
+      const size_t o2 = ooff(b + 2), o3 = ooff(b + 3);
+      jn0 = l4[o2];
+      jn1 = l4[o3];
+      cn0 = c4[o2];
+      cn1 = c4[o3];
       const bool second = b + 1 < nbo;  // entries of the second block are the list's
       const uint32_t sl[8] = {j0.x, j0.y, j0.z, j0.w, second ? j1.x : (uint32_t)d.n,
                               second ? j1.y : (uint32_t)d.n, second ? j1.z : (uint32_t)d.n,
