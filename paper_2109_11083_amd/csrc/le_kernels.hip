@@ -280,8 +280,9 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
 // (2) Exclusive scan of the cell counts into cell_start, one pass with
 // decoupled look-back: block b scans kScanTile cells (8 consecutive per
 // thread), publishes its total in status word b (flag 1), adds the totals of
-// its predecessors walking back until one has published its inclusive prefix
-// (flag 2), and publishes its own.  A word packs flag << 62 | value, so one
+// its predecessors walking back (64 at a time, one per lane of the first
+// wave) until one has published its inclusive prefix (flag 2), and publishes
+// its own.  A word packs flag << 62 | value, so one
 // 64-bit atomic carries both.  Every block publishes its total before it
 // waits, and all blocks are resident at once (at most a few dozen), so every
 // wait ends; a bounded spin latches LE_E_STATE rather than hang.  The counts
@@ -315,30 +316,46 @@ __global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) {
     if (w < wid) woff += wsum[w];
     agg += wsum[w];
   }
-  if (threadIdx.x == 0) {
+  if (wid == 0) {
+    // look back with the whole first wave: lane l reads the word of block
+    // p - l, so one round covers 64 predecessors; the prefix is the sum of
+    // the aggregates up to and including the nearest inclusive prefix
     unsigned long long* st = d.scan_status;
+    const unsigned long long vmask = (1ull << 62) - 1ull;
     long long prefix = 0;
-    if (b == 0) {
-      __hip_atomic_store(&st[0], scan_word(2, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&st[b], scan_word(1, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int p = b - 1;
-      long long spins = 0;
-      while (p >= 0) {
-        const unsigned long long w = __hip_atomic_load(&st[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int flag = (int)(w >> 62);
-        if (flag == 0) {
-          if (++spins > (1ll << 24)) { latch(d.flags, LE_E_STATE); break; }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+    if (lane == 0)
+      __hip_atomic_store(&st[b], scan_word(b == 0 ? 2 : 1, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int p = b - 1;
+    long long spins = 0;
+    while (p >= 0) {
+      const int q = p - lane;
+      // before block 0 the prefix is an inclusive 0
+      const unsigned long long w =
+          q >= 0 ? __hip_atomic_load(&st[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : scan_word(2, 0);
+      const int flag = (int)(w >> 62);
+      const unsigned long long inc = __ballot(flag == 2);
+      const unsigned long long zero = __ballot(flag == 0);
+      const int first2 = inc ? __builtin_ctzll(inc) : 64;
+      const unsigned long long need = first2 >= 63 ? ~0ull : ((2ull << first2) - 1ull);
+      if (zero & need) {  // a predecessor in reach has not published yet
+        if (++spins > (1ll << 22)) {
+          if (lane == 0) latch(d.flags, LE_E_STATE);
+          break;
         }
-        prefix += (long long)(w & ((1ull << 62) - 1ull));
-        if (flag == 2) break;
-        --p;
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      __hip_atomic_store(&st[b], scan_word(2, prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      long long val = lane <= first2 ? (long long)(w & vmask) : 0;
+      for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
+      prefix += val;
+      if (first2 < 64) break;
+      p -= 64;
     }
-    base_sh = prefix;
+    if (lane == 0) {
+      if (b > 0)
+        __hip_atomic_store(&st[b], scan_word(2, prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      base_sh = prefix;
+    }
   }
   __syncthreads();
   int run = (int)base_sh + woff + incl - tot;
@@ -569,35 +586,31 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
       tot_prev += wtot;
       __syncthreads();
     }
-    // a piece is staged iff it ends within the halo; the staged set is a prefix
+    // a piece is staged iff it ends within the halo; the staged set is a
+    // prefix of the pieces (the running offsets only grow).  The staging
+    // table is that prefix, one entry per piece in order (empty ones too:
+    // the search below skips them), written by the piece's own thread.
+    if (threadIdx.x == 0) { pc.nseg = 0; pc.ntot = 0; }
+    __syncthreads();
     for (int rd = 0; rd < 2; ++rd) {
       int e = rd * kTile + (int)threadIdx.x;
       if (pt && e < npieces) {
         int t = e / kPieces, q = e % kPieces;
         bool real = q < pc.npc[t];
         int start_off = incl[rd] - cnt[rd];
-        pc.off[t][q] = (real && incl[rd] <= kHalo) ? start_off : -1;
+        const bool fits = incl[rd] <= kHalo;
+        pc.off[t][q] = (real && fits) ? start_off : -1;
+        pc.s_off[e] = start_off;
+        pc.s_start[e] = real ? pc.start[t][q] : 0;
+        pc.s_code[e] = real ? pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1) : 0;
+        if (fits) {
+          atomicMax(&pc.nseg, e + 1);
+          atomicMax(&pc.ntot, incl[rd]);
+        }
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int ns = 0, off = 0;
-      for (int e = 0; e < npieces; ++e) {
-        int t = e / kPieces, q = e % kPieces;
-        if (pc.off[t][q] < 0) continue;
-        if (pc.count[t][q] > 0) {
-          pc.s_off[ns] = pc.off[t][q];
-          pc.s_start[ns] = pc.start[t][q];
-          pc.s_code[ns] = pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1);
-          ++ns;
-        }
-        off = pc.off[t][q] + pc.count[t][q];
-      }
-      pc.s_off[ns] = off;
-      pc.nseg = ns;
-      pc.ntot = off;
-      d.tile_nstage[tile] = off;
-    }
+    if (threadIdx.x == 0) d.tile_nstage[tile] = pc.ntot;
   }
   __syncthreads();
   // ---- stage positions and record their slots (flat, four loads in flight)
