@@ -485,10 +485,11 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
 // Two threads per particle: thread t (half 0) and t + kTile (half 1) split
 // each (dy, dz) range in two and write two sub-lists, which the force kernel
 // consumes with two threads per particle in the same way.
+template <int HALO>
 __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
-  __shared__ float hx[kHalo + 8], hy[kHalo + 8], hz[kHalo + 8];
+  __shared__ float hx[HALO + 8], hy[HALO + 8], hz[HALO + 8];
   __shared__ Pieces pc;
   // per-thread ring of list entries, and a spare entry for rejected ones
   __shared__ __align__(16) uint16_t lbuf[2 * kTile][16];
@@ -598,7 +599,7 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
         int t = e / kPieces, q = e % kPieces;
         bool real = q < pc.npc[t];
         int start_off = incl[rd] - cnt[rd];
-        const bool fits = incl[rd] <= kHalo;
+        const bool fits = incl[rd] <= HALO;
         pc.off[t][q] = (real && fits) ? start_off : -1;
         pc.s_off[e] = start_off;
         pc.s_start[e] = real ? pc.start[t][q] : 0;
@@ -642,7 +643,7 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
         const int h = h0 + u * blockDim.x;
         // written unconditionally (past the halo: a spare entry) so that the
         // loads above are not sunk into the condition one by one
-        const int hw = h < tot ? h : kHalo + 7;
+        const int hw = h < tot ? h : HALO + 7;
         int sx, sy, sz;
         unpack_img((uint8_t)code[u], sx, sy, sz);
         hx[hw] = (float)((pj[u].x + ((double)sy * Delta + (double)sx * d.Lx)) - org.x);
@@ -715,7 +716,7 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
       const int lim = b - h0;
       unsigned keep = lim >= 8 ? 0xffu : (lim > 0 ? (1u << lim) - 1u : 0u);
       if (sq >= h0 && sq < h0 + 8) keep &= ~(1u << (sq - h0));
-      const int hc = min(h0, kHalo);
+      const int hc = min(h0, HALO);
       unsigned m_in = 0u, m_band = 0u;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1688,7 +1689,10 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
                      force ? 1 : 0, control ? 1 : 0);
   hipLaunchKernelGGL(k_cell_scan, dim3((d.ncell + kScanTile - 1) / kScanTile), dim3(kScanBlock), 0, s, dn);
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
-  hipLaunchKernelGGL(k_neighbors, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  // the LDS halo of the search: full size when the force kernel restages it,
+  // smaller (more blocks per CU) when the lists hold global slots
+  if (dn.staged) hipLaunchKernelGGL(k_neighbors<kHalo>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  else hipLaunchKernelGGL(k_neighbors<kHaloSearch>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
   return hipGetLastError();
 }
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
