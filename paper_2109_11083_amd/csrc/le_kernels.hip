@@ -1187,34 +1187,45 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     };
     const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo);
     const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc);
-    uint4 jn0 = l4[ooff(0)], jn1 = l4[ooff(1)];
-    uint32_t cn0 = c4[ooff(0)], cn1 = c4[ooff(1)];
-    {
-    for (int b = 0; b < nbo; b += 2) {
-      const uint4 j0 = jn0, j1 = jn1;
-      const uint32_t c0 = cn0, c1 = cn1;
-      const size_t o2 = ooff(b + 2), o3 = ooff(b + 3);
-      jn0 = l4[o2];
-      jn1 = l4[o3];
-      cn0 = c4[o2];
-      cn1 = c4[o3];
-      const bool second = b + 1 < nbo;  // entries of the second block are the list's
-      const uint32_t sl[8] = {j0.x, j0.y, j0.z, j0.w, second ? j1.x : (uint32_t)d.n,
-                              second ? j1.y : (uint32_t)d.n, second ? j1.z : (uint32_t)d.n,
-                              second ? j1.w : (uint32_t)d.n};
-      double4 pj[8];
+    // GB blocks of 4 per round: one for the plain global layout (fewer
+    // gathers in flight leave room for more waves: KG 49 -> 48 us), two with
+    // the halo's remainder pieces and with DPD (one block: 138 -> 195 us)
+    constexpr int GB = (STAGED || DPD) ? 2 : 1;
+    uint4 jn[GB];
+    uint32_t cn[GB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) pj[u] = P[sl[u]];
+    for (int k = 0; k < GB; ++k) { jn[k] = l4[ooff(k)]; cn[k] = c4[ooff(k)]; }
+    {
+    for (int b = 0; b < nbo; b += GB) {
+      uint4 jq[GB];
+      uint32_t cq[GB];
+      uint32_t sl[4 * GB];
+#pragma unroll
+      for (int k = 0; k < GB; ++k) {
+        jq[k] = jn[k];
+        cq[k] = cn[k];
+        const size_t o = ooff(b + GB + k);
+        jn[k] = l4[o];
+        cn[k] = c4[o];
+        const bool in = b + k < nbo;  // the entries of this block are the list's
+        sl[4 * k] = in ? jq[k].x : (uint32_t)d.n;
+        sl[4 * k + 1] = in ? jq[k].y : (uint32_t)d.n;
+        sl[4 * k + 2] = in ? jq[k].z : (uint32_t)d.n;
+        sl[4 * k + 3] = in ? jq[k].w : (uint32_t)d.n;
+      }
+      double4 pj[4 * GB];
+#pragma unroll
+      for (int u = 0; u < 4 * GB; ++u) pj[u] = P[sl[u]];
       // DPD: the partners' velocities and tags, one 32-byte gather each
-      double4 vj[DPD ? 8 : 1];
+      double4 vj[DPD ? 4 * GB : 1];
       if (DPD) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) vj[u] = VT[sl[u]];
+        for (int u = 0; u < 4 * GB; ++u) vj[u] = VT[sl[u]];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 4 * GB; ++u) {
         int sx, sy, sz;
-        unpack_img((uint8_t)((u < 4 ? c0 : c1) >> (8 * (u & 3))), sx, sy, sz);
+        unpack_img((uint8_t)(cq[u >> 2] >> (8 * (u & 3))), sx, sy, sz);
         sx += sy * W;
         double dy = (pi.y - pj[u].y) - (double)sy * d.Ly;
         double dx = ((pi.x - pj[u].x) - (double)sy * Delta) - (double)sx * d.Lx;
