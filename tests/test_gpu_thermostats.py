@@ -244,3 +244,77 @@ def test_peculiar_storage_lj_trajectory(skin):
     assert np.abs(got["sum_mc2"] - want["sum_mc2"]).max() < 1e-6
     assert np.abs(got["com"] - want["com"]).max() < 1e-9
     sim.close()
+
+
+def _two_gpu(xi, xj, ui, uj, L=6.0, shear_rate=0.0, gamma=2.0):
+    x = np.array([xi, xj], dtype=float).T.copy()
+    u = np.array([ui, uj], dtype=float).T.copy()
+    p = Params(n=2, box=(L, L, L), shear_rate=shear_rate, gamma=gamma, kT=0.0, eps=0.0, rc=1.0, skin=0.3,
+               thermostat="dpd")
+    sim = Sim(p, x, u)
+    _, _, f, _ = sim.state()
+    sim.close()
+    return f
+
+
+def test_dpd_two_particles_by_hand_on_gpu():
+    """The hand values of the oracle's two-particle pins, through the GPU
+    path: 0.5 apart, approaching at speed 1, gamma 2 -> drag 0.5; across the
+    sheared face the image's streaming velocity makes particles at rest in the
+    lab frame separate."""
+    F = _two_gpu([1.0, 1.0, 1.0], [1.5, 1.0, 1.0], [1.0, 0.3, -0.2], [0.0, 0.0, 0.0])
+    assert np.abs(F[:, 0] - np.array([-0.5, 0.0, 0.0])).max() < 1e-15
+    assert np.abs(F[:, 1] - np.array([0.5, 0.0, 0.0])).max() < 1e-15
+    L, sr, g = 6.0, 0.1, 2.0
+    F = _two_gpu([1.3, 0.2, 1.0], [1.0, L - 0.3, 1.0], [0, 0, 0], [0, 0, 0], L=L, shear_rate=sr, gamma=g)
+    d = np.array([0.3, 0.5, 0.0])
+    r = np.linalg.norm(d)
+    e = d / r
+    expect = -g * (1.0 - r) ** 2 * (e[0] * sr * L) * e
+    assert np.allclose(F[:, 0], expect, rtol=1e-13, atol=1e-16)
+    assert np.allclose(F[:, 1], -expect, rtol=1e-13, atol=1e-16)
+
+
+def test_angle_term_by_hand_on_gpu():
+    """Right-angle trimer with only the angle term (no pair force, FENE
+    constant 0): F_a = (0, -k, 0), F_b = (-k, 0, 0), F_j = (k, k, 0); a
+    straight trimer feels nothing."""
+    k = 1.5
+    for xs, want in (
+            ([[3.0, 2.0, 2.0], [2.0, 2.0, 2.0], [2.0, 3.0, 2.0]],
+             [[0.0, -k, 0.0], [k, k, 0.0], [-k, 0.0, 0.0]]),
+            ([[1.0, 2.0, 2.0], [2.0, 2.0, 2.0], [3.0, 2.0, 2.0]], [[0.0] * 3] * 3)):
+        x = np.array(xs).T.copy()
+        p = Params(n=3, box=(10.0, 10.0, 10.0), eps=0.0, rc=1.0, skin=0.3, n_chains=1, chain_len=3,
+                   fene_k=0.0, angle_k=k, gamma=0.0, kT=0.0)
+        sim = Sim(p, x, np.zeros((3, 3)))
+        F, W = sim.forces()
+        sim.close()
+        assert np.abs(F.T - np.array(want)).max() < 1e-15, (F.T, want)
+
+
+def test_peculiar_storage_msd_and_profile():
+    """Unwrapped coordinates and the lab flow profile with stored peculiar
+    velocities, against the oracle run beside it."""
+    w = inputs.lj_workload(n_side=8, shear_rate=1.0, seed=13)
+    L = w.box[1]
+    c0 = np.asarray(w.u).copy()
+    c0[0] -= 1.0 * (np.asarray(w.x)[1] - L / 2)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=1.0, seed=13, skin=0.3, dt=0.01, kT=2.0,
+               velocity="peculiar")
+    sim = Sim(p, w.x, c0)
+    ref = O.Sim(w.x, c0, _oracle_params(p))
+    r_gpu = sim.unwrapped(host=False)
+    r0 = sim.unwrapped()
+    unw = ref.x[1:].copy()
+    r_ref = unw.copy()
+    for _ in range(3):
+        sim.step(25)
+        unw = ref.run_tracked(25, unw)
+        assert np.abs((sim.unwrapped() - r0) - (unw - r_ref)).max() < 1e-8
+        assert np.allclose(sim.msd(r_gpu), O.msd(unw, r_ref), rtol=1e-7)
+        got = sim.observables(8)
+        want = O.observables(ref.x, ref.u, ref.Delta, ref.p, nbins=8)
+        assert np.array_equal(got["count"], want["count"])
+        assert np.abs(got["sum_ux"] - want["sum_ux"]).max() < 1e-6
+    sim.close()
