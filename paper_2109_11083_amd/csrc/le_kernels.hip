@@ -491,9 +491,8 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[HALO + 8], hy[HALO + 8], hz[HALO + 8];
   __shared__ Pieces pc;
-  // per-thread ring of list entries, and a spare entry for rejected ones
+  // per-thread ring of list entries
   __shared__ __align__(16) uint16_t lbuf[2 * kTile][16];
-  __shared__ uint16_t lspare[2 * kTile];
   __shared__ int cnt1[kTile];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
@@ -752,16 +751,16 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
         }
         continue;
       }
-      // append the accepted LDS indices into a ring of 16 per lane (rejected
-      // ones go to the spare entry); a completed block of 8 leaves as one
-      // 16-byte store
+      // append the accepted LDS indices into a ring of 16 per lane: every
+      // candidate is written at the next free entry and the count advances
+      // only for accepted ones (a rejected one is overwritten by the next
+      // write); a completed block of 8 leaves as one 16-byte store
+      int nn = npl;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int pos = (npl + __builtin_popcount(m_in & ((1u << u) - 1u))) & 15;
-        uint16_t* dst = ((m_in >> u) & 1u) ? &lbuf[threadIdx.x][pos] : &lspare[threadIdx.x];
-        *dst = (uint16_t)(h0 + u);
+        lbuf[threadIdx.x][nn & 15] = (uint16_t)(h0 + u);
+        nn += (int)((m_in >> u) & 1u);
       }
-      const int nn = npl + __builtin_popcount(m_in);
       if ((nn >> 3) != (npl >> 3)) {
         const int blk = npl >> 3;
         if ((blk + 1) * 8 <= K)
