@@ -259,6 +259,9 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
     const double list_pp = 4.0 / 3.0 * M_PI * g.rlist * g.rlist * g.rlist * rho;
     d->staged = (p->tune == 1) ? 1 : (p->tune == 2) ? 0 : (list_pp >= 3.0 * halo_pp ? 1 : 0);
     if (p->thermostat == LE_THERMO_DPD) d->staged = 0;
+    // a sparse system's tile halo (with a margin) fits the smaller search
+    // halo, which leaves room for more resident blocks
+    d->small_halo = (!d->staged && 1.15 * halo_pp * kTile <= kHaloSearch) ? 1 : 0;
   }
 }
 

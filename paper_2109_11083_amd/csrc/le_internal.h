@@ -83,6 +83,7 @@ struct Dev {
   int32_t n_bonded;                 // n_chains * chain_len (tags >= n_bonded are free)
   int32_t precision;
   int32_t staged;                  // 1: partners in the tile's LDS halo; 0: all from global memory
+  int32_t small_halo;              // 1: the list search stages at most kHaloSearch positions per tile
   // FP32 pre-test of the list build: r2 (float, tile-relative coordinates)
   // below nb_lo is certainly inside r_list^2, at or above nb_hi certainly
   // outside; in between the plain FP64 displacement decides.

@@ -1699,10 +1699,10 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
                      force ? 1 : 0, control ? 1 : 0);
   hipLaunchKernelGGL(k_cell_scan, dim3((d.ncell + kScanTile - 1) / kScanTile), dim3(kScanBlock), 0, s, dn);
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
-  // the LDS halo of the search: full size when the force kernel restages it,
-  // smaller (more blocks per CU) when the lists hold global slots
-  if (dn.staged) hipLaunchKernelGGL(k_neighbors<kHalo>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
-  else hipLaunchKernelGGL(k_neighbors<kHaloSearch>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  // the LDS halo of the search: full size, or smaller (more blocks per CU)
+  // for sparse systems whose lists hold global slots
+  if (dn.small_halo) hipLaunchKernelGGL(k_neighbors<kHaloSearch>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  else hipLaunchKernelGGL(k_neighbors<kHalo>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
   return hipGetLastError();
 }
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
