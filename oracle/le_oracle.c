@@ -591,6 +591,38 @@ static void dpd_pair_cb(void *ctx, int64_t i, int64_t j, const double d_in[3], d
     }
 }
 
+/* The DPD pair terms alone on a few chosen particles, each summed over every */
+/* other particle in increasing tag order (to check large systems by sample);  */
+/* out Gs[ns][3].  Same pair law as below, evaluated from i's side.             */
+void orc_dpd_sample(int64_t n, const double *x, const double *u, double Delta, const orc_params *p,
+                    int64_t step, int64_t ns, const int64_t *idx, double *Gs)
+{
+    const double sv = p->shear_rate * p->box[1];
+    const double rd2 = p->dpd_rc * p->dpd_rc;
+    const double pref = sqrt(24.0 * p->gamma * p->kT / p->dt);
+    double d[3];
+    int32_t img[3];
+    for (int64_t s = 0; s < ns; ++s) {
+        const int64_t i = idx[s];
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = orc_disp(x, n, i, j, Delta, p->box, d, img);
+            if (!(r2 < rd2)) continue;
+            double r = sqrt(r2);
+            double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+            double v[3] = {(u[i] - u[j]) - (double)img[1] * sv, u[n + i] - u[n + j],
+                           u[2 * n + i] - u[2 * n + j]};
+            double w = 1.0 - r / p->dpd_rc;
+            double ev = e[0] * v[0] + e[1] * v[1];
+            ev = ev + e[2] * v[2];
+            double f = -p->gamma * w * w * ev + pref * w * orc_dpd_theta(p->seed, step, i, j);
+            for (int a = 0; a < 3; ++a) acc[a] += f * e[a];
+        }
+        for (int a = 0; a < 3; ++a) Gs[3 * s + a] = acc[a];
+    }
+}
+
 static void thermostat_dpd(int64_t n, const double *x, const double *u, const double *Fc,
                            double *F, int64_t step, double Delta, const orc_params *p, int method)
 {

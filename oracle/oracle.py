@@ -96,6 +96,8 @@ def lib():
         L.orc_philox.restype = None
         L.orc_noise.argtypes = [C.c_uint64, C.c_int64, C.c_int64, dp]
         L.orc_noise.restype = None
+        L.orc_dpd_sample.argtypes = [C.c_int64, dp, dp, C.c_double, pp, C.c_int64, C.c_int64, i64p, dp]
+        L.orc_dpd_sample.restype = None
         L.orc_dpd_theta.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64]
         L.orc_dpd_theta.restype = C.c_double
         L.orc_stress.argtypes = [C.c_int64, dp, dp, dp, pp, dp]
@@ -151,6 +153,16 @@ def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, p
     p.angle_k = angle_k
     p.velocity = VELOCITIES[velocity] if isinstance(velocity, str) else int(velocity)
     return p
+
+
+def dpd_sample(x, u, Delta, p: Params, step, idx):
+    """DPD pair terms on the particles idx (ns, 3), brute force in tag order."""
+    x, u = _c64(x), _c64(u)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros((len(idx), 3))
+    lib().orc_dpd_sample(x.shape[1], _dp(x), _dp(u), Delta, C.byref(p), int(step), len(idx),
+                         idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out))
+    return out
 
 
 def dpd_theta(seed, step, ti, tj):

@@ -458,11 +458,13 @@ def test_full_size_lj_256k_sampled():
     sim.close()
 
 
-def test_full_size_kg_400k_sampled():
+@pytest.mark.parametrize("angle_k", [0.0, 1.5])
+def test_full_size_kg_400k_sampled(angle_k):
     """The Kremer-Grest melt at its benchmarked size (2000 chains x 200 beads,
-    WCA + FENE): cells bit-exact, pair set at r_list bit-exact, forces with
-    bonds at 300 sampled beads within 1e-12."""
-    w, p = _kg_case(n_chains=2000, chain_len=200, shear_rate=0.01)
+    WCA + FENE, with and without the cosine angle term): cells bit-exact,
+    pair set at r_list bit-exact, forces with bonds at 300 sampled beads
+    within 1e-12."""
+    w, p = _kg_case(n_chains=2000, chain_len=200, shear_rate=0.01, angle_k=angle_k)
     step0 = 4321
     sim = Sim(p, w.x, w.u, step0=step0)
     out = sim.build_cells()

@@ -318,3 +318,30 @@ def test_peculiar_storage_msd_and_profile():
         assert np.array_equal(got["count"], want["count"])
         assert np.abs(got["sum_ux"] - want["sum_ux"]).max() < 1e-6
     sim.close()
+
+
+def test_full_size_dpd_256k_sampled():
+    """The 256,000-particle LJ system with DPD (the DPD workload of the
+    benchmark) at its real size: total force of the initial state (LJ + DPD
+    pair terms with the noise of step0) at 300 sampled particles, including
+    particles next to the sheared faces, within 1e-12."""
+    w = inputs.lj_workload(n=256000, shear_rate=0.1, seed=21)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.1, seed=21, gamma=5.0, thermostat="dpd",
+               skin=0.2)
+    step0 = 999
+    _log("dpd 256k sampled")
+    sim = Sim(p, w.x, w.u, step0=step0)
+    _, _, F, st = sim.state()
+    assert st == step0
+    sim.close()
+    op = _oracle_params(p)
+    Delta = O.offset(step0, p.dt, p.shear_rate, p.box[0], p.box[1])
+    xw, uw = O.le_wrap(w.x, w.u, Delta, op)
+    rng = np.random.default_rng(5)
+    ys = np.argsort(xw[1])
+    idx = np.concatenate([ys[:75], ys[-75:], rng.choice(p.n, 150, replace=False)])
+    Fs = O.forces_sample(xw, Delta, op, idx) + O.dpd_sample(xw, uw, Delta, op, step0, idx)
+    rms = math.sqrt(float((Fs ** 2).sum(axis=1).mean()))
+    err = float(np.sqrt(((F[:, idx].T - Fs) ** 2).sum(axis=1)).max()) / rms
+    _log(f"  e_F={err:.3e}")
+    assert err <= 1e-12

@@ -211,3 +211,17 @@ def test_dpd_grid_and_brute_force_pairs_agree():
     b = O.Sim(w.x, w.u, p, step0=123, method=1)
     scale = np.abs(a.F).max()
     assert np.abs(a.F - b.F).max() < 1e-12 * scale
+
+
+def test_dpd_sampled_sum_matches_full_sum():
+    """The per-particle DPD sum used to check large systems equals the pair
+    loop of the thermostat (total force minus the conservative force)."""
+    w = inputs.lj_workload(n_side=8, shear_rate=0.6, seed=8)
+    p = O.make_params(w.x.shape[1], w.box, shear_rate=0.6, gamma=5.0, seed=8, thermostat="dpd")
+    step0 = 4242
+    sim = O.Sim(w.x, w.u, p, step0=step0, method=0)
+    Fc, _, _ = O.forces(sim.x, sim.Delta, p)
+    idx = np.array([0, 3, 77, 200, 311, 511])
+    G = O.dpd_sample(sim.x, sim.u, sim.Delta, p, step0, idx)
+    assert np.allclose(G, (sim.F - Fc)[:, idx].T, rtol=0, atol=1e-11 * np.abs(sim.F).max())
+    assert np.abs(G).max() > 1.0
