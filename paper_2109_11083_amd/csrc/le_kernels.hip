@@ -1038,20 +1038,25 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 // Langevin force (Eq. langevin on the peculiar velocity, Eq. vi):
 //   F = F^c - gamma m c + sqrt(24 gamma m kT / dt) theta,  c = u - gamma_dot (y - L_y/2) e_x
 // (with the friction on the lab velocity, c = u of the image inside the box).
-// With the LDS halo the block has two threads per particle: thread t and
-// t + kTile take alternate batches of the particle's list (twice the waves
-// per CU for the same LDS), and the second hands its partial sums to the
-// first through LDS before the epilogue.
+// With the LDS halo the block has kForceTPP threads per particle: threads
+// t, t + kTile, ... take every kForceTPP-th batch of the particle's list (more
+// waves per CU for the same LDS), and hand their partial sums to the first
+// through LDS before the epilogue.  Without the halo the launch bound of four
+// tiles per block makes the compiler keep fewer registers (more waves; DPD
+// 138 -> 132 us); the launch itself uses one tile.
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED>
-__global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__ f_out,
+__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force(Dev d, double* __restrict__ f_out,
                                                      double* __restrict__ sample_out) {
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
   constexpr bool DPD = MODE == kDpdForce;
   static_assert(!DPD || !STAGED, "DPD partners come from global memory");
   constexpr int kH = STAGED ? kHalo + 1 : 1;  // no halo: every partner from global memory
-  constexpr int kTh = STAGED ? 2 * kTile : kTile;  // threads per block
-  static_assert(!STAGED || kHalo + 1 >= kTile * 9, "the halo array holds the partial-sum exchange");
-  __shared__ double hx[kH], hy[kH], hz[kH];
+  constexpr int kTh = STAGED ? kForceTPP * kTile : kTile;  // threads per block
+  static_assert(!STAGED || 3 * kH >= kTile * 9 * (kForceTPP - 1), "the halo holds the partial-sum exchange");
+  __shared__ double hbuf[3 * kH];
+  double* const hx = hbuf;
+  double* const hy = hbuf + kH;
+  double* const hz = hbuf + 2 * kH;
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = d.flags->status;
@@ -1112,7 +1117,7 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
       code[u] = (h < nst) ? cv : pack_img(0, 0, 0);
     }
     t0 = l8[boff(half)];
-    t1 = l8[boff(half + 2)];
+    t1 = l8[boff(half + kForceTPP)];
     // every position is loaded and written (past nst: the sentinel slot, an
     // unused LDS entry), so that no load is sunk into a condition and all of
     // them are in flight together
@@ -1142,18 +1147,18 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     const double rc2 = d.rc2, sig2 = d.sig2, eps24 = d.eps24;
     // staged partners (already shifted to their image): the particle's two
     // sub-lists read as one sequence of batches of 8, of which this thread
-    // takes batches half, half + 2, ...; one 16-byte index load per batch,
-    // two of this thread's batches ahead.  Loads always read an existing block
+    // takes batches half, half + kForceTPP, ...; one 16-byte index load per
+    // batch, two of this thread's batches ahead.  Loads always read an existing block
     // of the list array and the value is selected afterwards (a select between
     // pointers would become a flat load).
     const int nb = STAGED ? nb0 + npl1_ld / kPlainBatch : 0;
     const uint4 zero4 = make_uint4(kHalo | (kHalo << 16), kHalo | (kHalo << 16), kHalo | (kHalo << 16),
                                    kHalo | (kHalo << 16));
     uint4 v0 = nb > half ? t0 : zero4;
-    uint4 v1 = nb > half + 2 ? t1 : zero4;
-    for (int b = half; b < nb; b += 2) {
-      uint4 t2 = l8[boff(b + 4)];
-      uint4 v2 = (b + 4 < nb) ? t2 : zero4;
+    uint4 v1 = nb > half + kForceTPP ? t1 : zero4;
+    for (int b = half; b < nb; b += kForceTPP) {
+      uint4 t2 = l8[boff(b + 2 * kForceTPP)];
+      uint4 v2 = (b + 2 * kForceTPP < nb) ? t2 : zero4;
       int j[8] = {(int)(v0.x & 0xffff), (int)(v0.x >> 16), (int)(v0.y & 0xffff), (int)(v0.y >> 16),
                   (int)(v0.z & 0xffff), (int)(v0.z >> 16), (int)(v0.w & 0xffff), (int)(v0.w >> 16)};
       double xj[8], yj[8], zj[8];
@@ -1175,9 +1180,11 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     // particle takes both as one sequence.
     // the sub-lists this thread takes, read as one sequence of blocks of 4
     // (sub-list s_lo, then s_hi) so that one prefetch pipeline runs across both
-    const int s_lo = STAGED ? half : 0, s_hi = STAGED ? half : 1;
-    const int nbo0 = d.n_og[s_lo * np + i] / kOtherBatch;
-    const int nbo = nbo0 + (s_hi != s_lo ? d.n_og[s_hi * np + i] / kOtherBatch : 0);
+    // (with the halo, threads 0 and 1 of a particle take one sub-list each)
+    const bool has_og = !STAGED || half < 2;
+    const int s_lo = STAGED ? min(half, 1) : 0, s_hi = STAGED ? s_lo : 1;
+    const int nbo0 = has_og ? d.n_og[s_lo * np + i] / kOtherBatch : 0;
+    const int nbo = nbo0 + (has_og && s_hi != s_lo ? d.n_og[s_hi * np + i] / kOtherBatch : 0);
     const int last_ob = d.K / kOtherBatch - 1;
     auto ooff = [&](int q) -> size_t {
       const bool first = q < nbo0;
@@ -1299,18 +1306,22 @@ __global__ void __launch_bounds__(2 * kTile) k_force(Dev d, double* __restrict__
     }
   }
   if (STAGED) {
-    // the second thread of each particle hands over its partial sums (the
-    // halo array is free once every thread has left the pair loops)
+    // the other threads of each particle hand over their partial sums (the
+    // halo array is free once every thread has left the pair loops); the
+    // first adds them in thread order
     __syncthreads();
-    double* ex = hx + tl * 9;
-    if (half == 1) {
+    if (half > 0) {
+      double* ex = hbuf + ((half - 1) * kTile + tl) * 9;
       ex[0] = fx; ex[1] = fy; ex[2] = fz;
       if (VIR) for (int q = 0; q < 6; ++q) ex[3 + q] = w[q];
     }
     __syncthreads();
     if (half == 0) {
-      fx += ex[0]; fy += ex[1]; fz += ex[2];
-      if (VIR) for (int q = 0; q < 6; ++q) w[q] += ex[3 + q];
+      for (int t = 1; t < kForceTPP; ++t) {
+        const double* ex = hbuf + ((t - 1) * kTile + tl) * 9;
+        fx += ex[0]; fy += ex[1]; fz += ex[2];
+        if (VIR) for (int q = 0; q < 6; ++q) w[q] += ex[3 + q];
+      }
     } else {
       for (int q = 0; q < 6; ++q) w[q] = 0.0;
     }
@@ -1721,7 +1732,7 @@ static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent
 template <int MODE, bool SAMPLE, bool STAGED>
 static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
                            hipEvent_t e1) {
-  dim3 g(d.ntiles), b(STAGED ? 2 * kTile : kTile);
+  dim3 g(d.ntiles), b(STAGED ? kForceTPP * kTile : kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if (mixed) {
