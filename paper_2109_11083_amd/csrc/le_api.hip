@@ -634,7 +634,7 @@ const char* le_strerror(le_status st) {
     case LE_E_WORKSPACE: return "workspace smaller than le_workspace_bytes()";
     case LE_E_BOND: return "FENE bond stretched to r >= R0";
     case LE_E_NONFINITE: return "non-finite position or velocity";
-    case LE_E_CAPACITY: return "neighbour list over capacity (raise max_neighbors)";
+    case LE_E_CAPACITY: return "neighbour list or cell occupancy over capacity (raise max_neighbors, or lower the density)";
     case LE_E_HIP: return "HIP runtime error";
     case LE_E_STATE: return "call not valid in the current state";
     default: return "unknown status";
