@@ -81,3 +81,34 @@ def test_observables_sums_and_in_box_velocity():
     assert np.allclose(ob2["sum_ux"], ob["sum_ux"], rtol=0, atol=1e-12)
     assert np.allclose(ob2["sum_mc2"], ob["sum_mc2"], rtol=1e-12)
     assert np.allclose(ob2["com"], ob["com"], rtol=0, atol=1e-14)
+
+
+@pytest.mark.slow
+def test_com_velocity_fluctuations_match_paper_ranges():
+    """Langevin on the peculiar velocity does not conserve momentum: each
+    CoM velocity component fluctuates with variance kT/(N m).  For the
+    paper's N = 2000 LJ fluid this puts 3 sigma at 0.047 (T = 0.5) and 0.082
+    (T = 1.5), inside the ranges the paper reports (golden fixture); a larger
+    friction than the paper's only shortens the correlation time, not the
+    variance."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "com_ranges.json")))
+    n = fx["n"]
+    for case in fx["cases"]:
+        kT, rng_ = case["kT"], case["range"]
+        w = inputs.lj_workload(n=n, shear_rate=0.1, kT=kT, seed=17)
+        p = O.make_params(w.x.shape[1], w.box, shear_rate=0.1, gamma=5.0, kT=kT, seed=17)
+        sim = O.Sim(w.x, w.u, p)
+        sim.run(200)
+        com = []
+        for _ in range(120):
+            sim.run(10)
+            com.append(O.observables(sim.x, sim.u, sim.Delta, sim.p, nbins=1)["com"])
+        com = np.array(com)
+        # gradient and vorticity components (the flow component also carries the
+        # small fluctuation of the mean streaming velocity)
+        sd = com[:, [1, 2]].std()
+        assert sd == pytest.approx(math.sqrt(kT / n), rel=0.2), (kT, sd)
+        assert 3 * math.sqrt(kT / n) < rng_
+        assert (np.abs(com[:, 2]) < rng_).mean() > 0.95
