@@ -485,14 +485,17 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
 // Two threads per particle: thread t (half 0) and t + kTile (half 1) split
 // each (dy, dz) range in two and write two sub-lists, which the force kernel
 // consumes with two threads per particle in the same way.
-template <int HALO>
+template <int HALO, bool GL>
 __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[HALO + 8], hy[HALO + 8], hz[HALO + 8];
   __shared__ Pieces pc;
-  // per-thread ring of list entries
-  __shared__ __align__(16) uint16_t lbuf[2 * kTile][16];
+  // per-thread ring of list entries: LDS indices (halo layout), or slots and
+  // image codes (GL: lists of global slots), left as whole blocks
+  __shared__ __align__(16) uint16_t lbuf[GL ? 1 : 2 * kTile][16];
+  __shared__ __align__(16) uint32_t gslot[GL ? 2 * kTile : 1][kOtherBatch];
+  __shared__ __align__(4) uint8_t gcode[GL ? 2 * kTile : 1][kOtherBatch];
   __shared__ int cnt1[kTile];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
@@ -680,6 +683,24 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   const float tlo = d.nb_lo, thi = d.nb_hi;
   const size_t hbase = (size_t)tile * kHalo;
   int npl = 0, nog = 0;
+  // one global-list entry: with GL into the lane's ring, a completed block of
+  // four leaving as one 16-byte and one 4-byte store; otherwise (rows beyond
+  // the halo of a halo-layout list) straight to global memory
+  auto og_append = [&](uint32_t slot, uint8_t code) {
+    if constexpr (GL) {
+      gslot[threadIdx.x][nog & 3] = slot;
+      gcode[threadIdx.x][nog & 3] = code;
+      ++nog;
+      if ((nog & 3) == 0 && nog <= K) {
+        const size_t b = (size_t)((nog >> 2) - 1) * np2 + v;
+        reinterpret_cast<uint4*>(d.nlo)[b] = *reinterpret_cast<const uint4*>(gslot[threadIdx.x]);
+        reinterpret_cast<uint32_t*>(d.nlc)[b] = *reinterpret_cast<const uint32_t*>(gcode[threadIdx.x]);
+      }
+    } else {
+      if (nog < K) { d.nlo[idx4(nog, v, np2)] = slot; d.nlc[idx4(nog, v, np2)] = code; }
+      ++nog;
+    }
+  };
   for (int c9 = 0; c9 < 9; ++c9) {
     const int dzc = c9 / 3 - 1, dyc = c9 % 3 - 1;
     int jz = iz + dzc, sz = jz < 0 ? -1 : (jz >= d.nz ? 1 : 0);
@@ -738,36 +759,32 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
                           (double)sz2 * d.Lz, (double)sy2 * Delta))
           m_in |= 1u << u;
       }
-      if (!d.staged) {
+      if constexpr (GL) {
         // lists without a force-time halo: the partner's slot and image code
         while (m_in) {
           const int u = __builtin_ctz(m_in);
           m_in &= m_in - 1u;
-          if (nog < K) {
-            d.nlo[idx4(nog, v, np2)] = (uint32_t)d.halo_slot[hbase + h0 + u];
-            d.nlc[idx4(nog, v, np2)] = d.halo_code[hbase + h0 + u];
-          }
-          ++nog;
+          og_append((uint32_t)d.halo_slot[hbase + h0 + u], d.halo_code[hbase + h0 + u]);
         }
-        continue;
-      }
-      // append the accepted LDS indices into a ring of 16 per lane: every
-      // candidate is written at the next free entry and the count advances
-      // only for accepted ones (a rejected one is overwritten by the next
-      // write); a completed block of 8 leaves as one 16-byte store
-      int nn = npl;
+      } else {
+        // append the accepted LDS indices into a ring of 16 per lane: every
+        // candidate is written at the next free entry and the count advances
+        // only for accepted ones (a rejected one is overwritten by the next
+        // write); a completed block of 8 leaves as one 16-byte store
+        int nn = npl;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        lbuf[threadIdx.x][nn & 15] = (uint16_t)(h0 + u);
-        nn += (int)((m_in >> u) & 1u);
+        for (int u = 0; u < 8; ++u) {
+          lbuf[threadIdx.x][nn & 15] = (uint16_t)(h0 + u);
+          nn += (int)((m_in >> u) & 1u);
+        }
+        if ((nn >> 3) != (npl >> 3)) {
+          const int blk = npl >> 3;
+          if ((blk + 1) * 8 <= K)
+            reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
+                *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
+        }
+        npl = nn;
       }
-      if ((nn >> 3) != (npl >> 3)) {
-        const int blk = npl >> 3;
-        if ((blk + 1) * 8 <= K)
-          reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
-              *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
-      }
-      npl = nn;
     }
     if (walk_global) {
       // this particle's cells of the row, read from global memory; the two
@@ -783,8 +800,7 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
           if (plain && q == i) continue;
           if (in_list_exact(d, pi, P[q], (double)sx * d.Lx, (double)sy * d.Ly, (double)sz * d.Lz,
                             (double)sy * Delta)) {
-            if (nog < K) { d.nlo[idx4(nog, v, np2)] = (uint32_t)q; d.nlc[idx4(nog, v, np2)] = code; }
-            ++nog;
+            og_append((uint32_t)q, code);
           }
         }
       }
@@ -810,14 +826,16 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
     latch(d.flags, LE_E_CAPACITY);
     npl_p = nog_p = 0;
   } else {
-    if (npl < npl_p) {  // pad and flush the partial block
-      const int blk = npl >> 3;
-      for (int r = npl; r < npl_p; ++r) lbuf[threadIdx.x][r & 15] = (uint16_t)kHalo;
-      reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
-          *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
+    if constexpr (!GL) {
+      if (npl < npl_p) {  // pad and flush the partial block
+        const int blk = npl >> 3;
+        for (int r = npl; r < npl_p; ++r) lbuf[threadIdx.x][r & 15] = (uint16_t)kHalo;
+        reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
+            *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
+      }
     }
     const uint8_t zero = pack_img(0, 0, 0);
-    for (int r = nog; r < nog_p; ++r) { d.nlo[idx4(r, v, np2)] = (uint32_t)n; d.nlc[idx4(r, v, np2)] = zero; }
+    while (nog < nog_p) og_append((uint32_t)n, zero);  // sentinel entries up to a whole block
   }
   d.n_plain[v] = npl_p;
   d.n_og[v] = nog_p;
@@ -1712,8 +1730,10 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
   // the LDS halo of the search: full size, or smaller (more blocks per CU)
   // for sparse systems whose lists hold global slots
-  if (dn.small_halo) hipLaunchKernelGGL(k_neighbors<kHaloSearch>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
-  else hipLaunchKernelGGL(k_neighbors<kHalo>, dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  if (dn.staged) hipLaunchKernelGGL((k_neighbors<kHalo, false>), dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  else if (dn.small_halo)
+    hipLaunchKernelGGL((k_neighbors<kHaloSearch, true>), dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
+  else hipLaunchKernelGGL((k_neighbors<kHalo, true>), dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
   return hipGetLastError();
 }
 hipError_t launch_kick_drift(const Dev& d, hipStream_t s) {
