@@ -1096,7 +1096,7 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_forc
   const int ic = valid ? i : 0;
   const int np2 = d.np2;
   const double4 pi_ld = P[ic];
-  const int npl0_ld = d.n_plain[ic], npl1_ld = d.n_plain[np + ic];
+  const int npl0_ld = STAGED ? d.n_plain[ic] : 0, npl1_ld = STAGED ? d.n_plain[np + ic] : 0;
   const double* Uv = d.vel[ac];
   const double u0_ld = Uv[ic], u1_ld = Uv[np + ic], u2_ld = Uv[2 * np + ic];
   const int tag_ld = d.tag[ac][ic];
