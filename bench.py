@@ -165,30 +165,42 @@ def serving_bench(count=64):
     return out
 
 
-def cpu_baseline(n, shear_rate, nsteps, thermostat="langevin"):
+def cpu_baseline(n, shear_rate, nsteps, thermostat="langevin", workload="lj"):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
-    w, p = lj_params(n, shear_rate, "fp64", thermostat=thermostat)
+    if workload == "kg":
+        w, p = kg_params(shear_rate, "fp64")
+        what = f"{p.n_chains} x {p.chain_len} Kremer-Grest melt"
+    else:
+        w, p = lj_params(n, shear_rate, "fp64", thermostat=thermostat)
+        what = f"{p.n}-particle LJ system"
     op = O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma,
-                       rc=p.rc, seed=p.seed, thermostat=thermostat)
+                       rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
+                       chain_len=p.chain_len, n_chains=p.n_chains, thermostat=thermostat)
     sim = O.Sim(w.x, w.u, op, step0=0, method=1)
     t0 = time.perf_counter()
     sim.run(nsteps)
     t1 = time.perf_counter()
     return dict(value=p.n * nsteps / (t1 - t0), unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"{nsteps} steps of the same {p.n}-particle LJ system (FP64 cell-list oracle, "
+                sample=f"{nsteps} steps of the same {what} (FP64 cell-list oracle, "
                        f"1 thread, {t1 - t0:.1f} s)")
 
 
 def kernel_hash():
+    """Hash of the kernel source: le_kernels.hip followed by le_internal.h (its
+    compile-time tile and halo sizes)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2109_11083_amd", "csrc", "le_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("le_kernels.hip", "le_internal.h"):
+        with open(os.path.join(ROOT, "paper_2109_11083_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic(name):
+def read_traffic(name, skin):
     """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary
-    (profiles/<name>.md), or None if it was taken on another kernel source."""
+    (profiles/<name>.md), or None if it was taken on another kernel source or
+    at another skin (other list lengths, other traffic)."""
     path = os.path.join(ROOT, "profiles", name + ".md")
     if not os.path.exists(path):
         return None
@@ -198,7 +210,12 @@ def read_traffic(name):
             if ":" in line and line.strip().startswith("- "):
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("le_kernels.hip sha256 prefix") != kernel_hash():
+    if vals.get("kernel source sha256 prefix") != kernel_hash():
+        return None
+    try:
+        if abs(float(vals["skin"]) - float(skin)) > 1e-9:
+            return None
+    except (KeyError, ValueError):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -216,7 +233,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--n", type=int, default=256000,
                     help="LJ particles: n sites of a ceil(n^(1/3))^3 lattice (256000 -> 64^3)")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps of the CPU baseline (default 12 for LJ, 40 for the KG melt: 10-20 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
@@ -273,7 +291,7 @@ def main():
     kname = ("k_force_kg400k_" if kg else ("k_force_dpd_lj256k_" if dpd else "k_force_lj256k_")) + args.precision
     if force_n > 0:
         avg_s = force_ms / 1e3 / force_n
-        traffic = read_traffic(kname + "_traffic")
+        traffic = read_traffic(kname + "_traffic", args.skin)
         if kg:
             # HBM-bound: algorithmic bytes of the fused step per particle
             achieved = r["n"] * BYTES_FUSED / avg_s / 1e9
@@ -333,8 +351,9 @@ def main():
         extra["serving"] = serving_bench(args.serve_requests)
 
     cpu = None
-    if not args.no_cpu_baseline and not kg:
-        cpu = cpu_baseline(args.n, sr, args.cpu_steps, thermostat=th)
+    if not args.no_cpu_baseline:
+        cpu_steps = args.cpu_steps if args.cpu_steps else (40 if kg else 12)
+        cpu = cpu_baseline(args.n, sr, cpu_steps, thermostat=th, workload=args.workload)
         log(f"bench: cpu oracle {cpu['value']:.4e} particle-steps/s")
 
     if kg:

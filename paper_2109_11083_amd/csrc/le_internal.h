@@ -11,7 +11,7 @@ namespace le {
 
 constexpr int kBlock = 256;        // threads per block of the streaming per-particle kernels
 constexpr int kTile = 128;         // particles (= threads) per tile of the pair kernels
-constexpr int kHalo = 2048;        // positions a tile stages in LDS (slot kHalo: far sentinel)
+constexpr int kHalo = 2560;        // positions a tile stages in LDS (slot kHalo: far sentinel)
 constexpr int kHaloSearch = 1536;  // the same for the list search alone (systems without a force-time halo)
 static_assert(kHaloSearch <= kHalo, "the halo tables are sized for kHalo");
 static_assert(kHalo % (4 * kTile) == 0, "halo staging loops assume whole rounds of the tile");
