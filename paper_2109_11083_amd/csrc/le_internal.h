@@ -15,7 +15,7 @@ constexpr int kHalo = 2560;        // positions a tile stages in LDS (slot kHalo
 constexpr int kHaloSearch = 1536;  // the same for the list search alone (systems without a force-time halo)
 static_assert(kHaloSearch <= kHalo, "the halo tables are sized for kHalo");
 static_assert(kHalo % (4 * kTile) == 0, "halo staging loops assume whole rounds of the tile");
-constexpr int kForceTPP = 2;       // threads per particle of the halo-layout force kernel
+constexpr int kForceTPP = 4;       // threads per particle of the halo-layout force kernel
 static_assert(kHalo % (kForceTPP * kTile) == 0, "halo staging rounds of the force kernel");
 constexpr int kMaxRows = 3;        // cell rows a tile may span and still be staged
 constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile
