@@ -463,9 +463,6 @@ struct Pieces {
   int sx0[kMaxRows * 9];
   int npc[kMaxRows * 9];
   int code[kMaxRows * 9];          // image code (sy, sz) of the row; sx added per piece
-  int s_off[kMaxRows * 9 * kPieces + 1];
-  int s_start[kMaxRows * 9 * kPieces];
-  int s_code[kMaxRows * 9 * kPieces];
   int nseg, ntot;
   TileGeom tg;
 };
@@ -484,19 +481,30 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
 
 // Two threads per particle: thread t (half 0) and t + kTile (half 1) split
 // each (dy, dz) range in two and write two sub-lists, which the force kernel
-// consumes with two threads per particle in the same way.
+// reads as one sequence of batches.
 template <int HALO, bool GL>
 __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[HALO + 8], hy[HALO + 8], hz[HALO + 8];
   __shared__ Pieces pc;
-  // per-thread ring of list entries: LDS indices (halo layout), or slots and
-  // image codes (GL: lists of global slots), left as whole blocks
-  __shared__ __align__(16) uint16_t lbuf[GL ? 1 : 2 * kTile][16];
+  // The staging table (one entry per piece: LDS offset, first slot, image
+  // code; read only while the halo is staged) and the per-thread ring of list
+  // entries (LDS indices of the halo layout, left as whole blocks; used only
+  // by the scan after the staging barrier) share their LDS.
+  union StageRing {
+    struct {
+      int off[kMaxRows * 9 * kPieces + 1];
+      int start[kMaxRows * 9 * kPieces];
+      int code[kMaxRows * 9 * kPieces];
+    } st;
+    uint16_t ring[GL ? 1 : 2 * kTile][16];
+  };
+  __shared__ __align__(16) StageRing sr;
+  auto& lbuf = sr.ring;
+  // with GL: the ring of slots and image codes of lists of global slots
   __shared__ __align__(16) uint32_t gslot[GL ? 2 * kTile : 1][kOtherBatch];
   __shared__ __align__(4) uint8_t gcode[GL ? 2 * kTile : 1][kOtherBatch];
-  __shared__ int cnt1[kTile];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
@@ -603,9 +611,9 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
         int start_off = incl[rd] - cnt[rd];
         const bool fits = incl[rd] <= HALO;
         pc.off[t][q] = (real && fits) ? start_off : -1;
-        pc.s_off[e] = start_off;
-        pc.s_start[e] = real ? pc.start[t][q] : 0;
-        pc.s_code[e] = real ? pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1) : 0;
+        sr.st.off[e] = start_off;
+        sr.st.start[e] = real ? pc.start[t][q] : 0;
+        sr.st.code[e] = real ? pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1) : 0;
         if (fits) {
           atomicMax(&pc.nseg, e + 1);
           atomicMax(&pc.ntot, incl[rd]);
@@ -631,10 +639,10 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
           int lo = 0, hi = nseg - 1;  // last segment with s_off <= h
           while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (pc.s_off[mid] <= h) lo = mid; else hi = mid - 1;
+            if (sr.st.off[mid] <= h) lo = mid; else hi = mid - 1;
           }
-          slot[u] = pc.s_start[lo] + (h - pc.s_off[lo]);
-          code[u] = pc.s_code[lo];
+          slot[u] = sr.st.start[lo] + (h - sr.st.off[lo]);
+          code[u] = sr.st.code[lo];
         }
       }
       double4 pj[4];
@@ -808,6 +816,10 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   }
   {  // telemetry (entries per particle, both sub-lists): one atomic per block
     __shared__ int wmax[2 * kTile / 64];
+    // the counts of the second halves go where the staged x coordinates
+    // were: every wave has left the scan after this barrier
+    __syncthreads();
+    int* cnt1 = reinterpret_cast<int*>(hx);
     if (half == 1) cnt1[tl] = npl + nog;
     __syncthreads();
     int mx = half == 0 ? npl + nog + cnt1[tl] : 0;
