@@ -109,6 +109,9 @@ def _check_cells_pairs(w_x, w_u, p: Params, step0):
     kg, kr = key(got), key(ref)
     assert len(kg) == len(np.unique(kg)), "pair listed twice"
     assert np.array_equal(kg, kr)
+    # rebuild telemetry: the largest list (partners within r_list, all images)
+    deg = np.bincount(np.concatenate([ref[:, 0], ref[:, 1]]).astype(np.int64), minlength=p.n)
+    assert sim.stats()["max_neighbors"] == int(deg.max())
     x, u, f, step = sim.state()
     assert step == step0
     assert np.array_equal(x, xw) and np.array_equal(u, uw)
