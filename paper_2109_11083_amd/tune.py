@@ -9,6 +9,7 @@ fastest is returned.
 from __future__ import annotations
 
 import dataclasses
+import math
 import time
 
 import torch
@@ -16,9 +17,26 @@ import torch
 from .sim import Params, Sim
 
 
-def autotune(p: Params, x0, u0, skins=(0.2, 0.3, 0.4, 0.5, 0.6, 0.8), tunes=(0,), steps=400,
-             warmup=100, step0=0):
-    """Return (best Params, table of (skin, tune, particle-steps/s))."""
+def filling_skin(p: Params, skin: float):
+    """Largest skin whose cell grid equals that of `skin`: the grid has
+    floor(L_a / (r_c + skin)) cells per axis, so every skin up to
+    min_a L_a / n_a - r_c searches the same cells and rebuilds less often.
+    None if the grid would be too coarse."""
+    r = p.rc + skin
+    nc = [int(math.floor(L / (r * (1.0 + 1e-9)))) for L in p.box]
+    if min(nc) < 3:
+        return None
+    return min(L / c for L, c in zip(p.box, nc)) / (1.0 + 1e-6) - p.rc
+
+
+def autotune(p: Params, x0, u0, skins=(0.2, 0.3, 0.4, 0.5, 0.6, 0.8), tunes=(0,), steps=1500,
+             warmup=200, step0=0, fill=True):
+    """Return (best Params, table of (skin, tune, particle-steps/s)).  With
+    `fill`, every candidate is replaced by its cell-filling skin (same cells,
+    fewer rebuilds)."""
+    if fill:
+        filled = [filling_skin(p, s) for s in skins]
+        skins = sorted({round(e, 6) for e in filled if e is not None and e > 0.0})
     table = []
     best = None
     for tune in tunes:
