@@ -111,7 +111,10 @@ def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIM
     phases = B.le_timing_read(sim.handle)
     st1 = sim.stats()
     sig = ring.cpu().numpy()
-    tail = sig[int(0.8 * len(sig)):]
+    # steady-state window: the second half of the timed steps (25 tau at 10,000
+    # steps of dt 0.005), ten blocks of 2.5 tau, much longer than the decay of
+    # the shear-stress correlations, for the standard error
+    tail = sig[int(0.5 * len(sig)):]
     eta = float(tail[:, 3].mean() / shear_rate) if shear_rate != 0 else None
     eta_se = None
     if len(tail) >= 20:
@@ -333,7 +336,9 @@ def main():
         extra[f"{args.workload}_{other}"] = dict(
             value=m["value"], force_kernel_us=1e3 * fm / max(fn, 1), eta=m["eta"], eta_se=m["eta_se"],
             eta_diff_vs_main=(m["eta"] - r["eta"]) if (r["eta"] is not None and m["eta"] is not None)
-            else None)
+            else None,
+            eta_diff_in_se=(abs(m["eta"] - r["eta"]) / math.hypot(m["eta_se"], r["eta_se"])
+                            if (m["eta_se"] and r["eta_se"]) else None))
         log(f"bench: {other}: {m['value']:.4e} p-steps/s eta={m['eta']}")
         if not kg:
             # Kremer-Grest melt, 2000 chains x 200 beads (HBM-bound pair kernel)
@@ -392,7 +397,8 @@ def main():
         "cpu_baseline": cpu,
         "rebuilds_per_1000_steps": round(1000.0 * r["rebuilds"] / args.steps, 2),
         "skin_autotune": tune_table,
-        "viscosity": {"eta": r["eta"], "block_se": r["eta_se"], "window": "last 20% of the timed steps"},
+        "viscosity": {"eta": r["eta"], "block_se": r["eta_se"],
+                      "window": "second half of the timed steps, 10 blocks"},
         "ux_profile_50_bins": [round(v, 5) for v in r["ux_profile"]],
         "kT_kinetic": r["kT"],
         "extra": extra,
