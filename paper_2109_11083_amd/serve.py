@@ -52,6 +52,7 @@ class Result:
     stress: np.ndarray      # [samples][6]
     state_x: np.ndarray | None = None
     state_u: np.ndarray | None = None
+    eta_se: float | None = None  # standard error of eta from 10 blocks of the window
 
     @property
     def latency(self) -> float:
@@ -145,13 +146,18 @@ class Server:
         sig = a.ring.cpu().numpy()
         half = sig[len(sig) // 2:]
         eta = float(half[:, 3].mean() / r.shear_rate)
+        eta_se = None
+        if len(half) >= 20:
+            blocks = half[: len(half) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / r.shear_rate
+            eta_se = float(blocks.std(ddof=1) / np.sqrt(10))
         xs = us = None
         if self.keep_state:
             xs, us, _, _ = a.sim.state()
         if a.graph is not None:
             a.graph.close()
         a.sim.close()
-        return Result(r.rid, r.arrival, a.admitted, now, r.n, r.steps, r.shear_rate, eta, sig, xs, us)
+        return Result(r.rid, r.arrival, a.admitted, now, r.n, r.steps, r.shear_rate, eta, sig, xs, us,
+                      eta_se=eta_se)
 
     def run(self, trace, realtime=True):
         """Serve the trace; returns the results in request order and a summary."""
