@@ -105,7 +105,7 @@ struct Dev {
   int32_t* cell_of;                // cell of each slot (binning pass)
   int32_t* rank;                   // arrival rank inside the cell (binning pass)
   int32_t bcap;                    // bucket capacity per cell
-  int32_t* bucket;                 // [ncell][bcap] slots binned into each cell (arrival order)
+  int32_t* bucket;                 // [ncell][bcap] tags binned into each cell (arrival order)
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
   // Neighbour lists: two sub-lists per particle (v = h * np + i, h = 0, 1,

@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
   if (cell >= 0) {
     const int r = base + (lane - run0);
     d.rank[i] = r;
-    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = i;
+    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = d.tag[sc.aux_cur][i];
     else latch(d.flags, LE_E_CAPACITY);
   }
 }
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_permute(Dev d) {
   const int t = tag[i];
   const int32_t* B = d.bucket + (size_t)cell * d.bcap;
   int r = 0;
-  for (int q = 0; q < cnt; ++q) r += (tag[B[q]] < t) ? 1 : 0;
+  for (int q = 0; q < cnt; ++q) r += (B[q] < t) ? 1 : 0;  // the bucket holds the cell's tags
   const int ns = s0 + r;
   reinterpret_cast<double4*>(d.pos[pd])[ns] = reinterpret_cast<const double4*>(d.pos[ps])[i];
   for (int a = 0; a < 3; ++a) {
