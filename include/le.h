@@ -92,7 +92,7 @@ typedef int32_t le_status;
                                 F_j -= the same; theta_ij shared by the pair.  Conserves momentum.
                                 Requires the global-memory pair layout (tune 0 or 2).           */
 #define LE_THERMO_LANGEVIN_LAB 2 /* Eq. langevin with the friction on the lab velocity u (the
-                                paper's xi_abs, Section 3.2): F_i += -gamma m u_i + noise       */
+                                paper's xi_abs, Section 3.1): F_i += -gamma m u_i + noise       */
 
 /* Velocity storage (Section 2.2, Eq. vi).  The velocity arrays given to
  * le_init and returned by le_get_state are the stored velocities.          */

@@ -646,7 +646,7 @@ static void thermostat_dpd(int64_t n, const double *x, const double *u, const do
 /* c = u - shear_rate (y - L_y/2) e_x (Eqs. shear-rate, vi): the total force  */
 /* on one particle is F^c - gamma m c + sqrt(24 gamma m kT / dt) theta.       */
 /* Thermostat 2 applies the friction to the lab velocity u instead (the      */
-/* paper's xi_abs, Section 3.2), which drags the flow profile.  With         */
+/* paper's xi_abs, Section 3.1), which drags the flow profile.  With         */
 /* peculiar storage u already is c.                                          */
 static void thermostat(int64_t n, const double *x, const double *u, const double *Fc,
                        double *F, int64_t step, const orc_params *p)

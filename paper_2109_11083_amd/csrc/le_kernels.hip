@@ -866,21 +866,24 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
 
 // ---------------------------------------------------------- integrator
 // Block maximum of |c|^2 into one of the kSlots words; called by every
-// thread of the block.
-__device__ __forceinline__ void vmax_commit(const Dev& d, double v2) {
-  __shared__ double wm[kBlock / 64];
+// thread of a block of exactly NTH threads (the LDS array holds one entry per
+// wave of that block; launches pass the kernel's own block size).
+template <int NTH>
+__device__ __forceinline__ void vmax_commit(const Dev& d, double v2, int lb) {
+  static_assert(NTH % 64 == 0 && NTH <= 1024, "whole waves, at most 16");
+  __shared__ double wm[NTH / 64];
   double m = wave_max(v2);
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = fmax(m, wm[w]);
-    atomicMax(&d.vmax[(blockIdx.x % kSlots) * kLineU64], (unsigned long long)__double_as_longlong(m));
+    for (int w = 1; w < NTH / 64; ++w) m = fmax(m, wm[w]);
+    atomicMax(&d.vmax[(lb % kSlots) * kLineU64], (unsigned long long)__double_as_longlong(m));
   }
 }
 
 // Sum the per-block stress partials (fixed order) and write the stress
 // -(K + W)/V, or with virial_only the pair virial W, into out6.  Called by one
-// whole block.
+// whole block of kBlock threads.
 __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
   __shared__ double red[kBlock / 64][kStressComps];
   double acc[kStressComps];
@@ -900,7 +903,7 @@ __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
   __syncthreads();
   if (threadIdx.x < 6) {
     double kin = 0.0, vir = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
+    for (int w = 0; w < kBlock / 64; ++w) {
       kin += red[w][threadIdx.x];
       vir += red[w][6 + threadIdx.x];
     }
@@ -939,7 +942,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
     if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
   }
-  vmax_commit(d, v2);
+  vmax_commit<kBlock>(d, v2, blockIdx.x);
 }
 
 // ---------------------------------------------------------- force kernel
@@ -1037,10 +1040,13 @@ __device__ __forceinline__ void dpd_pair(const Dev& d, uint32_t s_lo, uint32_t s
 }
 
 // Block reduction of 12 per-thread sums into partials[block][12] (fixed
-// order: wave butterflies, then waves in index order).
+// order: wave butterflies, then waves in index order).  Called by every thread
+// of a block of exactly NTH threads (one LDS row per wave of that block).
+template <int NTH>
 __device__ __forceinline__ void block_partials(double* vals, double* out, int lb,
                                                int nwrite = kStressComps) {
-  __shared__ double red[kBlock / 64][kStressComps];  // blockDim.x <= kBlock
+  static_assert(NTH % 64 == 0 && NTH <= 1024, "whole waves, at most 16");
+  __shared__ double red[NTH / 64][kStressComps];
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kStressComps; ++k) {
@@ -1051,7 +1057,7 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
   __syncthreads();
   if (threadIdx.x < nwrite) {
     double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < NTH / 64; ++w) s += red[w][threadIdx.x];
     out[lb * kStressComps + threadIdx.x] = s;
   }
 }
@@ -1419,12 +1425,12 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_forc
       U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
     }
   }
-  if (MODE == kStepFused) vmax_commit(d, v2);
+  if (MODE == kStepFused) vmax_commit<kTh>(d, v2, lb);
   if (VIR) {
     double vals[kStressComps];
 #pragma unroll
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.5 * w[k]; }
-    block_partials(vals, d.partials, lb);
+    block_partials<kTh>(vals, d.partials, lb);
   }
 }
 
@@ -1489,12 +1495,12 @@ __global__ void __launch_bounds__(kTile) k_integrate(Dev d) {
     }
     U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
   }
-  if (!LAST) vmax_commit(d, v2);
+  if (!LAST) vmax_commit<kTile>(d, v2, blockIdx.x);
   if (SAMPLE) {
     double vals[kStressComps];
 #pragma unroll
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.0; }
-    block_partials(vals, d.partials, blockIdx.x, 6);
+    block_partials<kTile>(vals, d.partials, blockIdx.x, 6);
   }
 }
 

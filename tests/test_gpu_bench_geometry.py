@@ -1,0 +1,283 @@
+"""GPU parity at the geometries the benchmark runs, and the tighter stress bars.
+
+The benchmark runs the autotuned list skins (cell-filling skins: 0.553808
+for the 256,000-particle LJ fluid, 22^3 cells; 0.60603 for the 2000 x 200
+Kremer-Grest melt, 45^3 cells; 0.299324 for the LJ fluid under DPD, 24^3
+cells), so the halo occupancy, the staged pieces and the remainder lists
+differ from those of the default skin.  Each case here starts the full-size
+system at that skin, compares the step-0 forces with the FP64 oracle, then
+advances 10 steps with le_step (steps 1-9 through the fused force /
+thermostat / integrator kernel, step 10 through its last-step form, stress
+sampled at steps 5 and 10) beside the oracle run of the same 10 steps.
+
+Stress bar (FP64): e_sigma = |d sigma_xy| / max(|sigma_xy,ref|, 1e-3 S_xy)
+with S_xy = (1/V)(sum_i m |c_x c_y| + sum_{i<j} |d_x F_ij,y|), the scale of
+the terms of the shear stress (Section 2.4, Eq. tensor); e_sigma <= 1e-12
+in FP64 and <= 1e-4 in mixed precision.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2109_11083_amd import inputs
+from paper_2109_11083_amd.sim import Params, Sim
+
+pytestmark = pytest.mark.gpu
+
+SKIN_LJ256K = 0.5538082032508997    # 22^3 cells of the 256k LJ box
+SKIN_KG400K = 0.6060300842332511    # 45^3 cells of the 400k KG box
+SKIN_DPD256K = 0.29932418631332514  # 24^3 cells of the 256k LJ box
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _op(p: Params, **over):
+    kw = dict(shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma, mass=p.mass, eps=p.eps,
+              sigma=p.sigma, rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
+              chain_len=p.chain_len, n_chains=p.n_chains, thermostat=p.thermostat, dpd_rc=p.dpd_rc,
+              velocity=p.velocity, angle_k=p.angle_k)
+    kw.update(over)
+    return O.make_params(p.n, p.box, **kw)
+
+
+def e_F(F, Fref):
+    rms = math.sqrt(float((Fref ** 2).sum(axis=0).mean()))
+    return float(np.sqrt(((F - Fref) ** 2).sum(axis=0)).max()) / rms
+
+
+def _le_disp(x, i, j, Delta, box):
+    """Lees-Edwards nearest-image displacements x_i - x_j of many pairs (for the
+    stress scale only; the pins of the displacement itself are the oracle's)."""
+    Lx, Ly, Lz = box
+    dy = x[1, i] - x[1, j]
+    sy = np.round(dy / Ly)
+    dy = dy - sy * Ly
+    dx = (x[0, i] - x[0, j]) - sy * Delta
+    dx = dx - np.round(dx / Lx) * Lx
+    dz = x[2, i] - x[2, j]
+    dz = dz - np.round(dz / Lz) * Lz
+    return dx, dy, dz
+
+
+def shear_scale(x, u, Delta, p: Params):
+    """S_xy = (1/V)(sum_i m |c_x c_y| + sum_{i<j} |d_x F_ij,y|) over the pair
+    (LJ/WCA) and bond terms of state (x, u) (x wrapped)."""
+    V = p.box[0] * p.box[1] * p.box[2]
+    cx = u[0] - p.shear_rate * (x[1] - 0.5 * p.box[1])
+    kin = p.mass * np.abs(cx * u[1]).sum()
+    pr = O.pairs_cells(x, Delta, p.box, p.rc)
+    dx, dy, dz = _le_disp(x, pr[:, 0], pr[:, 1], Delta, p.box)
+    r2 = dx * dx + dy * dy + dz * dz
+    s2 = p.sigma ** 2 / r2
+    s6 = s2 ** 3
+    f = 24.0 * p.eps * s6 * (2.0 * s6 - 1.0) / r2
+    vir = np.abs(f * dx * dy).sum()
+    if p.n_chains > 0:
+        t = np.arange(p.n_chains * p.chain_len)
+        t = t[(t % p.chain_len) < p.chain_len - 1]
+        bx, by, bz = _le_disp(x, t, t + 1, Delta, p.box)
+        b2 = bx * bx + by * by + bz * bz
+        fb = -p.fene_k / (1.0 - b2 / p.fene_r0 ** 2)
+        vir += np.abs(fb * bx * by).sum()
+    return (kin + vir) / V
+
+
+def e_sigma(sig, sig_ref, S):
+    return abs(sig[3] - sig_ref[3]) / max(abs(sig_ref[3]), 1e-3 * S)
+
+
+# ------------------------------------------------------------------ stress bar
+@pytest.mark.parametrize("case", ["lj_c1_0.0", "lj_c1_0.4", "lj_c1_0.9", "kg_small"])
+def test_shear_stress_fp64_e_sigma_1e12(case):
+    """le_stress of a configuration against the oracle's Eq. tensor, FP64,
+    e_sigma <= 1e-12 (Section 2.4, Eqs. tensor, viscosity)."""
+    if case.startswith("lj"):
+        frac = float(case.split("_")[-1])
+        w = inputs.lj_workload(n_side=10, shear_rate=0.1, seed=11)
+        p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.1, seed=11)
+        step0 = int(round(frac * p.box[0] / (p.shear_rate * p.box[1] * p.dt)))
+    else:
+        w = inputs.kg_workload(20, 20, shear_rate=0.01, seed=31)
+        p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.01, seed=31, rc=2 ** (1 / 6), pair="wca",
+                   n_chains=20, chain_len=20, gamma=0.5, dt=0.01)
+        step0 = 777
+    sim = Sim(p, w.x, w.u, step0=step0)
+    sig = sim.stress()
+    op = _op(p)
+    Delta = O.offset(step0, p.dt, p.shear_rate, p.box[0], p.box[1])
+    xw, uw = O.le_wrap(w.x, w.u, Delta, op)
+    _, Wr, _ = O.forces(xw, Delta, op, 0)
+    sr = O.stress(xw, uw, Wr, op)
+    S = shear_scale(xw, uw, Delta, p)
+    es = e_sigma(sig, sr, S)
+    _log(f"{case}: sigma_xy {sig[3]:.6e} ref {sr[3]:.6e} S_xy {S:.3e} e_sigma {es:.3e}")
+    assert es <= 1e-12
+    sim.close()
+
+
+# ------------------------------------------------------------------ benchmark geometries
+def _lj256k(skin, precision="fp64", thermostat="langevin"):
+    w = inputs.lj_workload(n=256000, shear_rate=0.1, seed=21)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.1, seed=21, skin=skin, precision=precision,
+               rc=2.5, dt=0.005, kT=1.0, gamma=5.0 if thermostat == "dpd" else 1.0,
+               thermostat=thermostat)
+    return w, p
+
+
+def _kg400k(skin):
+    w = inputs.kg_workload(2000, 200, shear_rate=0.01, seed=31, layout="snake")
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.01, seed=31, skin=skin, rc=2 ** (1 / 6),
+               pair="wca", n_chains=2000, chain_len=200, dt=0.01, kT=1.0, gamma=0.5)
+    return w, p
+
+
+def _cells(p: Params):
+    return tuple(int(math.floor(L / (p.rlist * (1 + 1e-9)))) for L in p.box)
+
+
+@pytest.mark.parametrize("case", ["lj256k", "kg400k", "dpd256k"])
+def test_benchmark_geometry_ten_steps(case):
+    if case == "lj256k":
+        w, p = _lj256k(SKIN_LJ256K)
+        ncell = 22
+    elif case == "kg400k":
+        w, p = _kg400k(SKIN_KG400K)
+        ncell = 45
+    else:
+        w, p = _lj256k(SKIN_DPD256K, thermostat="dpd")
+        ncell = 24
+    assert _cells(p) == (ncell,) * 3
+    _log(f"{case}: n={p.n} skin={p.skin} cells={ncell}^3")
+    op = _op(p)
+    sim = Sim(p, w.x, w.u, step0=0)
+    # step 0: conservative forces and virial (k_force without the integrator)
+    F, W = sim.forces()
+    ref = O.Sim(w.x, w.u, op, step0=0)
+    Fc, Wc, _ = ref.conservative()
+    ef0 = e_F(F, Fc)
+    ew0 = np.abs(W - Wc).max() / np.abs(Wc).max()
+    # total force of step 0 (conservative + thermostat of step 0)
+    x0, u0, f0, st0 = sim.state()
+    eft = e_F(f0, ref.F)
+    _log(f"{case}: step 0 e_F(conservative)={ef0:.3e} e_W={ew0:.3e} e_F(total)={eft:.3e}")
+    assert ef0 <= 1e-12 and ew0 <= 1e-12 and eft <= 1e-12
+    assert st0 == 0 and np.array_equal(x0, ref.x)
+    # 10 steps: 1..9 fused, 10 last; stress samples at 5 and 10
+    ring = sim.step(10, sample_every=5).cpu().numpy()
+    sref = ref.run(10, sample_every=5)
+    gx, gu, gf, st = sim.state()
+    assert st == 10 == ref.step
+    L = np.array(p.box)[:, None]
+    dx = gx - ref.x
+    dx = dx - L * np.round(dx / L)
+    cg = gu[0] - p.shear_rate * (gx[1] - p.box[1] / 2)
+    cr = ref.u[0] - p.shear_rate * (ref.x[1] - p.box[1] / 2)
+    du = max(np.abs(cg - cr).max(), np.abs(gu[1:] - ref.u[1:]).max())
+    ef = e_F(gf, ref.F)
+    es = np.abs(ring - sref).max() / np.abs(sref[:, :3]).max()
+    stats = sim.stats()
+    _log(f"{case}: 10 steps max|dx|={np.abs(dx).max():.3e} max|dc|={du:.3e} e_F={ef:.3e} "
+         f"ring={es:.3e} rebuilds={stats['rebuilds']} max_nb={stats['max_neighbors']}")
+    assert np.abs(dx).max() < 1e-10
+    assert du < 1e-9
+    assert ef < 1e-9
+    assert es < 1e-9
+    sim.close()
+
+
+def test_mixed_256k_sampled_forces_and_stress():
+    """Mixed precision at the benchmarked LJ geometry: forces of 400 sampled
+    particles within e_F <= 1e-5 of the FP64 oracle, the shear stress within
+    e_sigma <= 1e-4."""
+    w, p = _lj256k(SKIN_LJ256K, precision="mixed")
+    step0 = 7777
+    sim = Sim(p, w.x, w.u, step0=step0)
+    F, W = sim.forces()
+    sig = sim.stress()
+    op = _op(p)
+    Delta = O.offset(step0, p.dt, p.shear_rate, p.box[0], p.box[1])
+    xw, uw = O.le_wrap(w.x, w.u, Delta, op)
+    rng = np.random.default_rng(5)
+    ys = np.argsort(xw[1])
+    idx = np.concatenate([ys[:100], ys[-100:], rng.choice(p.n, 200, replace=False)])
+    Fs = O.forces_sample(xw, Delta, op, idx)
+    rms = math.sqrt(float((Fs ** 2).sum(axis=1).mean()))
+    ef = float(np.sqrt(((F[:, idx].T - Fs) ** 2).sum(axis=1)).max()) / rms
+    _, Wr, _ = O.forces(xw, Delta, op, 1)
+    sr = O.stress(xw, uw, Wr, op)
+    S = shear_scale(xw, uw, Delta, p)
+    es = e_sigma(sig, sr, S)
+    _log(f"mixed 256k: e_F={ef:.3e} sigma_xy {sig[3]:.6e} ref {sr[3]:.6e} e_sigma={es:.3e}")
+    assert ef <= 1e-5
+    assert es <= 1e-4
+    sim.close()
+
+
+def test_mixed_stress_along_100_steps():
+    """Mixed-precision run of 100 steps of the sheared LJ system: every 10th
+    step the sampled stress (the ring written by le_step) against the FP64
+    oracle's stress of the very state the run reached (e_sigma <= 1e-4), and
+    the trajectory against the FP64 oracle run beside it."""
+    w = inputs.lj_workload(n_side=10, shear_rate=0.5, seed=11)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.5, seed=11, skin=0.3, precision="mixed")
+    sim = Sim(p, w.x, w.u)
+    op = _op(p)
+    ref = O.Sim(w.x, w.u, op)
+    worst = 0.0
+    for k in range(10):
+        ring = sim.step(10, sample_every=10).cpu().numpy()[0]
+        ref.run(10)
+        x, u, f, st = sim.state()
+        Delta = O.offset(st, p.dt, p.shear_rate, p.box[0], p.box[1])
+        _, Wr, _ = O.forces(x, Delta, op, 0)
+        sr = O.stress(x, u, Wr, op)
+        es = e_sigma(ring, sr, shear_scale(x, u, Delta, p))
+        worst = max(worst, es)
+        assert es <= 1e-4, (k, es)
+    L = np.array(p.box)[:, None]
+    dx = x - ref.x
+    dx = dx - L * np.round(dx / L)
+    _log(f"mixed 100 steps: worst e_sigma={worst:.3e} max|dx| vs FP64 oracle={np.abs(dx).max():.3e}")
+    # FP32 force law: ~1e-6 relative per step, grown by the chaotic dynamics over 0.5 tau
+    assert np.abs(dx).max() < 1e-4
+    sim.close()
+
+
+def test_nve_energy_with_lazy_lists():
+    """gamma = 0, kT = 0, no shear, skin 0.4: 2000 steps of the LJ system
+    (lists reused between rebuilds, positions wrapped only at rebuilds); the
+    total energy of the states the run reaches, evaluated by the oracle with
+    the shifted LJ energy (Eq. lj-shift), stays within the drift of the
+    truncated-force dynamics.  A list that went incomplete (a late rebuild)
+    would show as a jump."""
+    w = inputs.lj_workload(n_side=10, shear_rate=0.0, seed=11)
+    p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.0, seed=11, skin=0.4, gamma=0.0, kT=0.0)
+    op = _op(p, lj_shift=O.lj_energy_shift(2.5))
+    sim = Sim(p, w.x, w.u)
+
+    def total(x, u):
+        return O.energy(x, 0.0, op) + 0.5 * p.mass * float((u ** 2).sum())
+
+    x, u, _, _ = sim.state()
+    e0 = total(x, u)
+    es = []
+    r0 = sim.stats()["rebuilds"]
+    for _ in range(10):
+        sim.step(200)
+        x, u, _, _ = sim.state()
+        es.append(total(x, u))
+    es = np.array(es)
+    rebuilds = sim.stats()["rebuilds"] - r0
+    drift = np.abs(es - e0).max() / p.n
+    jump = np.abs(np.diff(es)).max() / p.n
+    _log(f"NVE skin 0.4: e0/N={e0 / p.n:.6f} max drift/N={drift:.3e} max jump/N={jump:.3e} "
+         f"rebuilds={rebuilds}")
+    assert rebuilds > 10 + 10  # lazy rebuilds beyond the 10 forced by the state reads
+    assert drift < 2e-3
+    sim.close()

@@ -1,5 +1,5 @@
 """GPU parity of the DPD thermostat, of the Langevin friction on the lab
-velocity (Section 2.2; xi_DPD and xi_abs of Section 3.2) and of the
+velocity (Section 2.2; xi_DPD and xi_abs of Section 3.1) and of the
 peculiar-velocity storage (Section 2.2) against the oracle.
 
 DPD pair sums are accumulated in list order on the GPU and in (i, j) order in

@@ -155,7 +155,7 @@ def test_dpd_gas_linear_profile_under_shear():
     assert slope == pytest.approx(sr, rel=0.08)
     assert abs(icpt + sr * L / 2) < 0.25
     # viscous heating: DPD removes it only through relative motion, so the
-    # gas runs warmer than kT (Section 3.2 reports the same at high shear)
+    # gas runs warmer than kT (Section 3.1 reports the same at high shear)
     assert 1.0 < np.mean(ks) < 1.4
 
 
@@ -180,7 +180,7 @@ def test_lab_velocity_langevin_equals_peculiar_without_shear():
 def test_lab_velocity_langevin_flattens_profile():
     """With the friction on the lab velocity every particle is pulled towards
     rest, so between the sheared faces the mean flow decays and the profile
-    loses the imposed slope (Section 3.2); the peculiar form keeps it."""
+    loses the imposed slope (Section 3.1); the peculiar form keeps it."""
     sr, gamma = 0.8, 1.0
     out = {}
     for th in ("langevin", "langevin_abs"):
