@@ -121,6 +121,12 @@ typedef struct le_params {
   double fene_r0;      /* FENE maximal bond length R0                               */
   double dpd_rc;       /* cutoff r_c of the DPD weight omega (Eq. omega); 0 = rc;
                           must not exceed rc (the pair list covers rc only)      */
+  double force_cap;    /* > 0: every LJ/WCA pair force is capped in magnitude,
+                          |F_ij| <= force_cap (direction kept; bonds and angles
+                          uncapped).  For the warm-up of overlapping starts (a
+                          random-walk melt) before the equilibration that precedes
+                          shear (Section 2.4); 0 = the plain force law.  Requires
+                          LE_FP64, not LE_THERMO_DPD; uses the global pair layout. */
   double angle_k;      /* cosine angle term of the chains (Eq. angle), read as
                           V = angle_k (1 + cos theta) per consecutive bead triple,
                           theta the angle at the middle bead (minimum at 180

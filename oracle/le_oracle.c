@@ -33,6 +33,7 @@ typedef struct {
     double lj_shift;    /* energy shift added to every pair inside rc (energy only) */
     double dpd_rc;      /* DPD weight-function cutoff (thermostat 1) */
     double angle_k;     /* cosine angle term k_a (Eq. angle); 0 = none */
+    double force_cap;   /* > 0: pair-force magnitude limit of a warm-up run; 0 = none */
     uint64_t seed;
     int64_t n;
     int64_t n_chains;
@@ -313,6 +314,15 @@ static void pair_lj(double r2, const orc_params *p, double *f, double *e)
     double s12 = s6 * s6;
     *f = 24.0 * p->eps * (2.0 * s12 - s6) / r2;
     *e = 4.0 * p->eps * (s12 - s6) + p->lj_shift;
+    /* Warm-up of overlapping starts (the equilibration before shear of      */
+    /* Section 2.4): the magnitude |f| r of the pair force is limited to     */
+    /* force_cap, its direction kept.  The energy is left as it is (it is    */
+    /* not used while capped).                                               */
+    if (p->force_cap > 0.0) {
+        double lim = p->force_cap / sqrt(r2);
+        if (*f > lim) *f = lim;
+        if (*f < -lim) *f = -lim;
+    }
 }
 
 /* O8. FENE bond (Eq. fene): V = -1/2 k R0^2 ln(1 - r^2/R0^2) for r < R0,     */

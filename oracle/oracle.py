@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("lj_shift", C.c_double),
         ("dpd_rc", C.c_double),
         ("angle_k", C.c_double),
+        ("force_cap", C.c_double),
         ("seed", C.c_uint64),
         ("n", C.c_int64),
         ("n_chains", C.c_int64),
@@ -134,7 +135,7 @@ class OracleError(RuntimeError):
 def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, pair="lj",
                 eps=1.0, sigma=1.0, rc=2.5, fene_k=30.0, fene_r0=1.5, lj_shift=0.0,
                 seed=1, chain_len=0, n_chains=0, thermostat="langevin", dpd_rc=0.0, velocity="lab",
-                angle_k=0.0,
+                angle_k=0.0, force_cap=0.0,
                 **_ignored) -> Params:
     p = Params()
     for a in range(3):
@@ -151,6 +152,7 @@ def make_params(n, box, shear_rate=0.0, dt=0.005, kT=1.0, gamma=1.0, mass=1.0, p
     p.thermostat = THERMOSTATS[thermostat] if isinstance(thermostat, str) else int(thermostat)
     p.dpd_rc = dpd_rc if dpd_rc > 0 else rc
     p.angle_k = angle_k
+    p.force_cap = force_cap
     p.velocity = VELOCITIES[velocity] if isinstance(velocity, str) else int(velocity)
     return p
 

@@ -58,6 +58,7 @@ class le_params(C.Structure):
         ("fene_k", C.c_double),
         ("fene_r0", C.c_double),
         ("dpd_rc", C.c_double),
+        ("force_cap", C.c_double),
         ("angle_k", C.c_double),
         ("n_chains", C.c_int64),
         ("seed", C.c_uint64),

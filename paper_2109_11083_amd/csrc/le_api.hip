@@ -75,6 +75,9 @@ le_status validate(const le_params* p, Geometry* g) {
     // for r < rc), in the global-memory layout
     if (!(p->dpd_rc >= 0.0) || p->dpd_rc > rc || p->tune == 1) return LE_E_ARG;
   }
+  if (!(p->force_cap >= 0.0) || !isfinite(p->force_cap)) return LE_E_ARG;
+  if (p->force_cap > 0.0 && (p->precision != LE_FP64 || p->thermostat == LE_THERMO_DPD || p->tune == 1))
+    return LE_E_ARG;  // the capped force law exists for the FP64 global-memory layout
   if (p->chain_len < 0 || p->n_chains < 0) return LE_E_ARG;
   if (p->n_chains > 0) {
     if (p->chain_len < 2 || p->n_chains * (int64_t)p->chain_len > p->n) return LE_E_ARG;
@@ -234,6 +237,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->fene_k = p->fene_k;
   d->fene_r02 = p->fene_r0 * p->fene_r0;
   d->angle_k = (p->n_chains > 0 && p->chain_len >= 3) ? p->angle_k : 0.0;
+  d->force_cap = p->force_cap;
   d->inv_vol = 1.0 / (p->box[0] * p->box[1] * p->box[2]);
   d->n = (int32_t)p->n;
   d->np = (int32_t)g.np;
@@ -258,7 +262,7 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
     const double halo_pp = 9.0 * (tile_cells + 2.0) * cell_n / kTile;
     const double list_pp = 4.0 / 3.0 * M_PI * g.rlist * g.rlist * g.rlist * rho;
     d->staged = (p->tune == 1) ? 1 : (p->tune == 2) ? 0 : (list_pp >= 3.0 * halo_pp ? 1 : 0);
-    if (p->thermostat == LE_THERMO_DPD) d->staged = 0;
+    if (p->thermostat == LE_THERMO_DPD || p->force_cap > 0.0) d->staged = 0;
     // a sparse system's tile halo (with a margin) fits the smaller search
     // halo, which leaves room for more resident blocks
     d->small_halo = (!d->staged && 1.15 * halo_pp * kTile <= kHaloSearch) ? 1 : 0;

@@ -76,6 +76,7 @@ struct Dev {
   double rc2, rlist, rlist2;       // cutoff^2, list radius, list radius^2
   double fene_k, fene_r02;
   double angle_k;                  // cosine angle term of the chains (0: none)
+  double force_cap;                // > 0: pair-force magnitude cap (warm-up of overlapping starts)
   double inv_vol;
   int32_t nx, ny, nz, ncell;
   int32_t n, np;                   // particles, padded stride (np > n: slot n is a far-away sentinel)

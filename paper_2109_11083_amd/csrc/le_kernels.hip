@@ -959,9 +959,12 @@ __device__ __forceinline__ void add_pair(double f, double dx, double dy, double 
 
 // Scalar LJ force factor f (force on i = f d) for r^2 = r2, zero outside the
 // cutoff.  Branch-free so that the candidates of one batch are independent
-// instruction streams the compiler can interleave.
-template <bool MIXED>
-__device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, double eps24) {
+// instruction streams the compiler can interleave.  With CAP (FP64 only) the
+// magnitude |f| r is limited to cap: |f| <= cap / r.
+template <bool MIXED, bool CAP = false>
+__device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, double eps24,
+                                            double cap = 0.0) {
+  static_assert(!(MIXED && CAP), "the capped force law is FP64");
   const bool in = r2 < rc2;
   if (MIXED) {
     float r2f = (float)r2;
@@ -980,6 +983,10 @@ __device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, 
     double s2 = sig2 * inv;
     double s6 = s2 * s2 * s2;
     double f = eps24 * s6 * fma(2.0, s6, -1.0) * inv;
+    if (CAP) {
+      const double lim = cap / sqrt(r2);
+      f = fmin(fmax(f, -lim), lim);
+    }
     return in ? f : 0.0;
   }
 }
@@ -1080,9 +1087,10 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 // through LDS before the epilogue.  Without the halo the launch bound of four
 // tiles per block makes the compiler keep fewer registers (more waves; DPD
 // 138 -> 132 us); the launch itself uses one tile.
-template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED>
+template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
 __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force(Dev d, double* __restrict__ f_out,
                                                      double* __restrict__ sample_out) {
+  static_assert(!CAP || (!STAGED && !MIXED && MODE != kDpdForce), "capped forces: FP64, global layout");
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
   constexpr bool DPD = MODE == kDpdForce;
   static_assert(!DPD || !STAGED, "DPD partners come from global memory");
@@ -1274,7 +1282,7 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_forc
         double dz = (pi.z - pj[u].z) - (double)sz * d.Lz;
         double r2 = dx * dx + dy * dy;
         r2 = r2 + dz * dz;
-        add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
+        add_pair<VIR>(lj_masked<MIXED, CAP>(r2, rc2, sig2, eps24, d.force_cap), dx, dy, dz, fx, fy, fz, w);
         if (DPD) {
           // the image s_y boxes up streams faster by s_y gamma_dot L_y
           const double vx = (u0_ld - vj[u].x) - (double)sy * d.sv;
@@ -1773,6 +1781,13 @@ static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* s
   dim3 g(d.ntiles), b(STAGED ? kForceTPP * kTile : kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
+  if constexpr (!STAGED && MODE != kDpdForce) {
+    if (d.force_cap > 0.0) {  // the host guarantees FP64 and the global layout
+      if (bonds) launch_k(k_force<MODE, false, true, SAMPLE, false, true>, g, b, s, e0, e1, d, f_out, so);
+      else launch_k(k_force<MODE, false, false, SAMPLE, false, true>, g, b, s, e0, e1, d, f_out, so);
+      return;
+    }
+  }
   if (mixed) {
     if (bonds) launch_k(k_force<MODE, true, true, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
     else launch_k(k_force<MODE, true, false, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);

@@ -48,6 +48,7 @@ class Params:
     dpd_rc: float = 0.0
     velocity: str = "lab"
     angle_k: float = 0.0
+    force_cap: float = 0.0
 
     def to_c(self) -> B.le_params:
         p = B.le_params()
@@ -69,6 +70,7 @@ class Params:
         p.dpd_rc = float(self.dpd_rc)
         p.velocity = VELOCITIES[self.velocity]
         p.angle_k = float(self.angle_k)
+        p.force_cap = float(self.force_cap)
         return p
 
     @property

@@ -111,3 +111,14 @@ def test_init_rejects_small_workspace_before_any_device_work():
 def test_strerror_is_static_text():
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(B.strerror(code), str) and B.strerror(code)
+
+
+def test_force_cap_is_validated_on_the_host():
+    ok = _lj(force_cap=100.0)
+    assert B.le_workspace_bytes(ok.to_c()) > 0
+    for bad in (_lj(force_cap=-1.0), _lj(force_cap=100.0, precision="mixed"),
+                _lj(force_cap=100.0, thermostat="dpd"), _lj(force_cap=100.0, tune=1),
+                _lj(force_cap=float("inf"))):
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(bad.to_c())
+        assert e.value.code == B.LE_E_ARG

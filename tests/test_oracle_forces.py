@@ -168,3 +168,35 @@ def test_kinetic_stress_of_a_single_particle():
     expect = -2.0 / V * np.array([c[0] * c[0], c[1] * c[1], c[2] * c[2], c[0] * c[1], c[0] * c[2],
                                   c[1] * c[2]])
     assert np.allclose(s, expect, rtol=1e-14, atol=1e-16)
+
+
+def test_force_cap_limits_the_magnitude_and_keeps_the_direction():
+    """Warm-up cap: a pair closer than the point where 24 (2 r^-13 - r^-7)
+    reaches the cap feels exactly the cap along d; a pair beyond it feels the
+    plain force; an attractive pair is capped symmetrically."""
+    cap = 100.0
+    p = O.make_params(2, (20.0, 20.0, 20.0), force_cap=cap)
+    p0 = O.make_params(2, (20.0, 20.0, 20.0))
+    # r = 3/4: plain force 24 (2 (4/3)^13 - (4/3)^7) = 1996.9... > cap
+    r = Fraction(3, 4)
+    plain = 24 * (2 * r ** -13 - r ** -7)
+    assert plain > cap
+    F, W, _ = O.forces(_two(float(r)), 0.0, p)
+    assert F[0, 0] == pytest.approx(cap, rel=1e-15) and F[0, 1] == -F[0, 0]
+    assert F[1, 0] == 0.0 and F[2, 0] == 0.0
+    assert W[0] == pytest.approx(float(r) * cap, rel=1e-15)
+    # a skewed pair: magnitude cap, direction d / r
+    x = np.array([[0.3, 0.0], [0.4, 0.0], [1.2, 1.0]])  # d = (0.3, 0.4, 0.2)
+    d = np.array([0.3, 0.4, 0.2])
+    F, _, _ = O.forces(x, 0.0, p)
+    assert np.linalg.norm(F[:, 0]) == pytest.approx(cap, rel=1e-14)
+    assert np.allclose(F[:, 0] / cap, d / np.linalg.norm(d), rtol=1e-14, atol=0)
+    # below the cap the force is untouched, bit for bit
+    for rr in (1.0, 1.12, 2.0):
+        Fa, _, _ = O.forces(_two(rr), 0.0, p)
+        Fb, _, _ = O.forces(_two(rr), 0.0, p0)
+        assert np.array_equal(Fa, Fb)
+    # an attractive force above a tiny cap: -cap along d
+    pt = O.make_params(2, (20.0, 20.0, 20.0), force_cap=1e-3)
+    F, _, _ = O.forces(_two(1.5), 0.0, pt)
+    assert F[0, 0] == pytest.approx(-1e-3, rel=1e-15)
