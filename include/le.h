@@ -284,6 +284,28 @@ le_status le_destroy(le_sim* s);
 /* Static description of a status code. */
 const char* le_strerror(le_status st);
 
+/* No-allocation variant of le_forces, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the conservative forces and pair virial of one
+ * configuration, computed exactly as le_init(p, x, u, NULL, ..., step) followed
+ * by le_forces() would (same kernels, same results), but with every
+ * intermediate (sorted copies, cells, neighbour lists, block partials) in a
+ * library-owned device array of 64 MiB per GPU instead of a caller workspace.
+ * No handle is created and nothing is allocated, on the host or the device.
+ *   p: as for le_init; le_workspace_bytes(p) must not exceed 64 MiB, else
+ *      LE_E_WORKSPACE (about 30,000 LJ particles at density 0.84, rc 2.5).
+ *   x: device float64 [3][n] by tag (wrapped with the offset of `step`).
+ *   f_out: device float64 [3][n] by tag, or NULL; virial6: device float64[6]
+ *      (W_ab as for le_forces), or NULL; at least one must be given.
+ *   status_out: device int32, or NULL: receives 0 or the LE_E_* code latched
+ *      on the device (bond, capacity, non-finite); when nonzero the outputs
+ *      are not written.
+ * Enqueued on hip_stream (a stream of the current device) and asynchronous.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * device (other streams, other host threads) race and give wrong results. */
+le_status le_forces_static(const le_params* p, const double* x, double* f_out, double* virial6,
+                           int32_t* status_out, int64_t step, void* hip_stream);
+
 /* Lees-Edwards offsets Delta_k for k = step0 .. step0+count-1 as the device
  * computes them (Eq. pos_new; fmod of shear_rate*L_y*(k*dt) by L_x, folded
  * into [0, L_x)).  out: device float64[count].  Enqueued on hip_stream. */

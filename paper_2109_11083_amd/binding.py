@@ -36,7 +36,7 @@ EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
     "le_timing_enable", "le_timing_read", "le_observables", "le_graph_create", "le_graph_launch",
-    "le_graph_destroy", "le_unwrapped", "le_msd",
+    "le_graph_destroy", "le_unwrapped", "le_msd", "le_forces_static",
 ]
 LE_MAX_BINS = 256
 
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
     L.le_graph_destroy.argtypes = [vp]
     L.le_unwrapped.argtypes = [vp, vp]
     L.le_msd.argtypes = [vp, vp, vp]
+    L.le_forces_static.argtypes = [P, vp, vp, vp, vp, i64, vp]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -225,6 +226,14 @@ def le_graph_launch(graph: int) -> None:
 
 def le_graph_destroy(graph: int) -> None:
     check(lib().le_graph_destroy(graph), "le_graph_destroy")
+
+
+def le_forces_static(p: le_params, x: int, f_out: int | None, virial6: int | None,
+                     status_out: int | None, step: int, stream: int | None) -> None:
+    """Forces and virial of one configuration in the library's own device
+    scratch (no workspace, no handle, nothing allocated)."""
+    check(lib().le_forces_static(C.byref(p), x, f_out, virial6, status_out, step, stream),
+          "le_forces_static")
 
 
 def le_timing_enable(sim: int, phases) -> None:

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -338,6 +339,38 @@ le_status read_status(le_sim* s) {
   return s->host_status;
 }
 
+// ---------------------------------------------------------------------------
+// Library-owned device scratch for le_forces_static: one array per GPU, held
+// from module load until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol; its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_addr.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+le_status scratch_addr(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LE_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return LE_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LE_E_HIP;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return LE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -643,6 +676,33 @@ const char* le_strerror(le_status st) {
     case LE_E_STATE: return "call not valid in the current state";
     default: return "unknown status";
   }
+}
+
+le_status le_forces_static(const le_params* p, const double* x, double* f_out, double* virial6,
+                           int32_t* status_out, int64_t step, void* hip_stream) {
+  if (!p || !x || (!f_out && !virial6)) return LE_E_ARG;
+  Geometry g;
+  le_status st = validate(p, &g);
+  if (st != LE_OK) return st;
+  if (carve(p, g, nullptr, nullptr, nullptr) > kStaticScratchBytes) return LE_E_WORKSPACE;
+  void* base = nullptr;
+  st = scratch_addr(&base);
+  if (st != LE_OK) return st;
+  // a handle on the stack over the scratch (nothing on the heap): the same
+  // launch sequence as le_init(x, u = 0) followed by le_forces
+  le_sim s{};
+  s.p = *p;
+  s.p.rc = g.rc;
+  s.stream = (hipStream_t)hip_stream;
+  carve(p, g, (char*)base, &s.d, &s);
+  fill_geometry(p, g, &s.d);
+  const double Delta0 = le_offset(step, p->dt, s.d.sv, p->box[0]);
+  st = hip_check(launch_load_state(s.d, s.stream, x, nullptr, nullptr, step, Delta0));
+  if (st == LE_OK) st = rebuild(&s, true, false);
+  if (st == LE_OK) st = hip_check(launch_force(s.d, s.stream, kForcesOnly, false, f_out, nullptr));
+  if (st == LE_OK && virial6) st = hip_check(launch_stress_final(s.d, s.stream, virial6, true));
+  if (st == LE_OK && status_out) st = hip_check(launch_status_out(s.d, s.stream, status_out));
+  return st;
 }
 
 le_status le_offsets(double shear_rate, double Lx, double Ly, double dt, int64_t step0, int64_t count,

@@ -176,6 +176,7 @@ hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t
                             unsigned long long* counter);
 hipError_t launch_load_state(const Dev& d, hipStream_t s, const double* x0, const double* u0,
                              const double* f0, int64_t step0, double Delta0);
+hipError_t launch_status_out(const Dev& d, hipStream_t s, int32_t* out);
 hipError_t launch_offsets(double sr, double Lx, double Ly, double dt, int64_t step0, int64_t count,
                           double* out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,

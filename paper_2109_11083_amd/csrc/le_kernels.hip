@@ -108,7 +108,7 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
     p.x = x0[i]; p.y = x0[n + i]; p.z = x0[2 * n + i]; p.w = 0.0;
     reinterpret_cast<double4*>(d.pos[0])[i] = p;
     for (int a = 0; a < 3; ++a) {
-      d.vel[0][a * np + i] = u0[a * n + i];
+      d.vel[0][a * np + i] = u0 ? u0[a * n + i] : 0.0;  // no velocities: particles at rest
       d.frc[0][a * np + i] = f0 ? f0[a * n + i] : 0.0;
     }
     d.tag[0][i] = i;
@@ -1720,6 +1720,11 @@ __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long lo
   }
 }
 
+// Copy the latched status word to a caller's device int32 (stream-ordered).
+__global__ void k_status_out(const Flags* __restrict__ f, int32_t* __restrict__ out) {
+  if (threadIdx.x == 0) *out = f->status;
+}
+
 // ------------------------------------------------------------- test hooks
 __global__ void k_offsets(double sv, double Lx, double dt, int64_t step0, int64_t count, double* out) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1873,6 +1878,11 @@ hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, i
 hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t cap,
                             unsigned long long* counter) {
   hipLaunchKernelGGL(k_pairs_out, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, pairs, cap, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_out(const Dev& d, hipStream_t s, int32_t* out) {
+  hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, s, d.flags, out);
   return hipGetLastError();
 }
 
