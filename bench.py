@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the Lees-Edwards shear-flow MD step on one MI355X.
 
-Workload (default): LJ fluid, N = 256,000 particles on 256,000 of the sites
-of a 64^3 simple-cubic lattice (seeded choice, jitter U(-0.05, 0.05)), density 0.8442, cutoff 2.5, T = 1, Langevin
-gamma = 1 on the peculiar velocity, shear rate 0.1 (flow x, gradient y),
-dt = 0.005, skin 0.3, float64, shear stress sampled every 10 steps.  One
-"step" is a full pass of the hot path: offset, rebuild test (and rebuild when
-due: crossing/wrap, sort, Lees-Edwards stencil, neighbour lists), pair forces,
-Langevin force, velocity Verlet, stress sample.
+Headline workload: the Kremer-Grest melt of 2000 linear chains x 200 beads
+(N = 400,000), built as random walks of bond 0.97 (non-reversal) at density
+0.85, WCA (r_c 2^(1/6)) + FENE (K 30, R0 1.5), kT 1, Langevin gamma 0.5 on
+the peculiar velocity, dt 0.01, shear rate 0.01 (flow x, gradient y), FP64,
+shear stress sampled every 10 steps.  Before the timed region the overlapping
+random-walk start is warmed up without shear with capped pair forces until
+the largest force is below 10^3 (paper Section 2.4: systems are equilibrated
+before shear); the list skin is autotuned on the warmed state.  One "step" is
+a full pass of the hot path: offset, rebuild test (and rebuild when due:
+crossing/wrap, sort, Lees-Edwards stencil, neighbour lists), pair + bond
+forces, Langevin force, velocity Verlet, stress sample.
 
 Prints ONE JSON line.  `value` is particle-steps/s with the state resident in
 HBM.  The roofline entry is for the dominant kernel (the fused force /
 thermostat / integrator kernel), timed with HIP events on the simulation's
 stream during the timed region.  The CPU baseline is the FP64 oracle
-(oracle/) on a bounded sample of the same workload, single thread.
+(oracle/, its OpenMP timing build on all host cores) on a bounded sample of
+the same workload.  Extras: the 256,000-particle LJ fluid (throughput, force
+kernel roofline, three shear rates), its viscosity in FP64 and mixed
+precision from fixed-length runs, the KG melt's viscosity at two shear rates
+in both precisions, the shear-rate sweep serving trace, and the oracle on
+every configuration with one thread and with all cores.
 """
 from __future__ import annotations
 
@@ -36,65 +45,102 @@ PAIR_FLOPS = 26.0             # per in-cutoff pair, counted once per unordered p
 STEP_FLOPS = 40.0             # thermostat + velocity Verlet per particle
 BYTES_FUSED = 100.0           # fused step, per particle: read x, u, tag; write x, u
 TIMING_FORCE = 0x1 | (8 << 8)  # event-time every 8th plain-step force launch (phase 0)
+ETA_STEPS = 25000             # fixed length of each viscosity run (independent of --steps)
+ETA_WARMUP = 2000
+ETA_WINDOW = 0.2              # last 20% of the samples (Fig. profile caption)
+
+LJ_GAMMA = {"langevin": 1.0, "langevin_abs": 1.0, "dpd": 5.0}
+DPD_PAIR_FLOPS = 30.0         # DPD dissipative + random pair terms (Philox is integer work)
+KG_CHAINS, KG_LEN = 2000, 200
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# friction per thermostat on the LJ fluid (the paper's xi = 1 Langevin, xi_DPD = 5)
-LJ_GAMMA = {"langevin": 1.0, "langevin_abs": 1.0, "dpd": 5.0}
-DPD_PAIR_FLOPS = 30.0         # DPD dissipative + random pair terms (Philox is integer work)
-
-
+# ------------------------------------------------------------------ workloads
 def lj_params(n, shear_rate, precision, seed=21, skin=0.3, thermostat="langevin"):
+    """LJ fluid: n of the sites of a ceil(n^(1/3))^3 lattice, density 0.8442, r_c 2.5."""
     from paper_2109_11083_amd import inputs
     from paper_2109_11083_amd.sim import Params
     w = inputs.lj_workload(n=n, shear_rate=shear_rate, seed=seed)
     p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, skin=skin,
                precision=precision, rc=2.5, dt=0.005, kT=1.0, gamma=LJ_GAMMA[thermostat],
                thermostat=thermostat)
-    return w, p
+    return w.x, w.u, p
 
 
-KG_CHAINS, KG_LEN = 2000, 200
-
-
-def kg_params(shear_rate, precision, seed=31, skin=0.3, n_chains=KG_CHAINS, chain_len=KG_LEN):
-    """Kremer-Grest melt: WCA + FENE(30, 1.5), density 0.85, T=1, gamma=0.5, dt=0.01,
-    overlap-free lattice-path start (stands in for the warmed-up random-walk melt)."""
+def kg_params(shear_rate, precision, skin=0.3, seed=31):
     from paper_2109_11083_amd import inputs
     from paper_2109_11083_amd.sim import Params
-    w = inputs.kg_workload(n_chains, chain_len, shear_rate=shear_rate, seed=seed, layout="snake")
-    p = Params(n=w.x.shape[1], box=w.box, shear_rate=shear_rate, seed=seed, skin=skin,
-               precision=precision, rc=2.0 ** (1.0 / 6.0), pair="wca", n_chains=n_chains,
-               chain_len=chain_len, dt=0.01, kT=1.0, gamma=0.5)
-    return w, p
+    L = inputs.box_for(KG_CHAINS * KG_LEN, inputs.KG_DENSITY)
+    return Params(n=KG_CHAINS * KG_LEN, box=(L, L, L), shear_rate=shear_rate, seed=seed, skin=skin,
+                  precision=precision, rc=2.0 ** (1.0 / 6.0), pair="wca", n_chains=KG_CHAINS,
+                  chain_len=KG_LEN, dt=0.01, kT=1.0, gamma=0.5)
 
 
-def pick_skin(n, shear_rate, precision, workload, thermostat="langevin"):
-    """Autotuned skin for a workload (short bursts; see paper_2109_11083_amd.tune)."""
+_KG_WARM = {}
+
+
+def kg_state(shear_rate, seed=31):
+    """The warmed random-walk melt (warm-up once per process, on the GPU, untimed),
+    with the streaming profile of `shear_rate` added to its thermal velocities."""
+    from paper_2109_11083_amd import inputs
+    from paper_2109_11083_amd.warmup import warm_up
+    if seed not in _KG_WARM:
+        w = inputs.kg_workload(KG_CHAINS, KG_LEN, shear_rate=0.0, seed=seed, layout="walk")
+        t0 = time.perf_counter()
+        x, c, info = warm_up(kg_params(0.0, "fp64", seed=seed), w.x, w.u)
+        log(f"bench: KG warm-up {info.steps} steps in {time.perf_counter() - t0:.1f} s, "
+            f"max force {info.max_force:.1f}")
+        _KG_WARM[seed] = (x, c, info)
+    x, c, info = _KG_WARM[seed]
+    u = inputs.streaming_initial_velocity(x, c, shear_rate, kg_params(0.0, "fp64").box[1])
+    return x, u, info
+
+
+def workload(name, shear_rate, precision, skin=0.3, n=256000, thermostat="langevin"):
+    """(x, u, Params) of a named workload."""
+    import dataclasses
+    if name == "kg":
+        x, u, _ = kg_state(shear_rate)
+        return x, u, kg_params(shear_rate, precision, skin=skin)
+    x, u, p = lj_params(n, shear_rate, precision, skin=skin, thermostat=thermostat)
+    return x, u, dataclasses.replace(p)
+
+
+def pick_skin(name, shear_rate, precision, n=256000, thermostat="langevin"):
+    """Autotuned skin (short bursts of the cell-filling skins; paper_2109_11083_amd.tune)."""
     from paper_2109_11083_amd.tune import autotune
-    if workload == "kg":
-        w, p = kg_params(shear_rate, precision)
-    else:
-        w, p = lj_params(n, shear_rate, precision, thermostat=thermostat)
-    best, table = autotune(p, w.x, w.u)
+    x, u, p = workload(name, shear_rate, precision, n=n, thermostat=thermostat)
+    best, table = autotune(p, x, u)
     return best.skin, [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
 
 
-def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIMING_FORCE, skin=0.3,
-            workload="lj", thermostat="langevin"):
+# ------------------------------------------------------------------ one timed run
+def eta_of(sig, shear_rate, window=ETA_WINDOW):
+    """Viscosity (Eq. viscosity) over the last `window` of the samples, with the
+    standard error of 10 block means."""
+    if shear_rate == 0 or len(sig) == 0:
+        return None, None
+    tail = sig[int(round((1.0 - window) * len(sig))):]
+    if len(tail) == 0:
+        return None, None
+    eta = float(tail[:, 3].mean() / shear_rate)
+    se = None
+    if len(tail) >= 20:
+        blocks = tail[: len(tail) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / shear_rate
+        se = float(blocks.std(ddof=1) / math.sqrt(10))
+    return eta, se
+
+
+def run_gpu(x, u, p, steps, warmup, sample_every=10, timing=TIMING_FORCE):
     """One timed run.  timing: le_timing_enable mask for HIP-event timing inside the
     timed region (bit 0: the plain-step force kernel; 0xF: every phase; bits 8..: stride)."""
     import torch
     from paper_2109_11083_amd import binding as B
     from paper_2109_11083_amd.sim import Sim
-    if workload == "kg":
-        w, p = kg_params(shear_rate, precision, skin=skin)
-    else:
-        w, p = lj_params(n, shear_rate, precision, skin=skin, thermostat=thermostat)
-    sim = Sim(p, w.x, w.u, step0=0)
+    sim = Sim(p, x, u, step0=0)
     ring = torch.zeros((max(steps // sample_every, 1), 6), dtype=torch.float64, device="cuda")
     if warmup > 0:
         wring = torch.zeros((max(warmup // sample_every, 1), 6), dtype=torch.float64, device="cuda")
@@ -110,22 +156,15 @@ def run_gpu(n, shear_rate, precision, steps, warmup, sample_every=10, timing=TIM
     t1 = time.perf_counter()
     phases = B.le_timing_read(sim.handle)
     st1 = sim.stats()
-    sig = ring.cpu().numpy()
-    # steady-state window: the second half of the timed steps (25 tau at 10,000
-    # steps of dt 0.005), ten blocks of 2.5 tau, much longer than the decay of
-    # the shear-stress correlations, for the standard error
-    tail = sig[int(0.5 * len(sig)):]
-    eta = float(tail[:, 3].mean() / shear_rate) if shear_rate != 0 else None
-    eta_se = None
-    if len(tail) >= 20:
-        blocks = tail[: len(tail) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / shear_rate
-        eta_se = float(blocks.std(ddof=1) / math.sqrt(10))
+    sig = ring.cpu().numpy()[: steps // sample_every]
+    eta, eta_se = eta_of(sig, p.shear_rate)
     prof = sim.observables(50)
     out = dict(n=p.n, seconds=t1 - t0, steps=steps, value=p.n * steps / (t1 - t0),
                ms_per_step=1e3 * (t1 - t0) / steps, phases=phases,
                rebuilds=st1["rebuilds"] - st0["rebuilds"], max_neighbors=st1["max_neighbors"],
                eta=eta, eta_se=eta_se, box=p.box, rc=p.rc,
-               ux_profile=[float(v) for v in prof["sum_ux"] / prof["count"]], kT=prof["kT"])
+               ux_profile=[float(v) for v in prof["sum_ux"] / np.maximum(prof["count"], 1)],
+               kT=prof["kT"])
     sim.close()
     return out
 
@@ -141,6 +180,94 @@ def copy_probe(mib=1024, reps=5):
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}),
           flush=True)
+
+
+# ------------------------------------------------------------------ roofline
+def kernel_hash():
+    """Hash of the kernel source: le_kernels.hip followed by le_internal.h (its
+    compile-time tile and halo sizes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("le_kernels.hip", "le_internal.h"):
+        with open(os.path.join(ROOT, "paper_2109_11083_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name, skin):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary
+    (profiles/<name>.md), or None if it was taken on another kernel source or
+    at another skin (other list lengths, other traffic)."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256 prefix") != kernel_hash():
+        return None
+    try:
+        if abs(float(vals["skin"]) - float(skin)) > 1e-9:
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline_of(r, kind, precision, skin, dpd=False):
+    """Roofline entry of the fused force kernel of run r (event-timed plain steps)."""
+    force_ms, force_n = r["phases"]["force"]
+    if force_n == 0:
+        return None
+    avg_s = force_ms / 1e3 / force_n
+    if kind == "kg":
+        name = "k_force_kg400k_" + precision
+        traffic = read_traffic(name + "_traffic", skin)
+        achieved = r["n"] * BYTES_FUSED / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic,
+                    bytes_per_particle=BYTES_FUSED,
+                    kernel="k_force (fused WCA + FENE force, Langevin, velocity Verlet), plain steps")
+    else:
+        name = ("k_force_dpd_lj256k_" if dpd else "k_force_lj256k_") + precision
+        traffic = read_traffic(name + "_traffic", skin)
+        rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
+        pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
+        flops_pp = (PAIR_FLOPS + (DPD_PAIR_FLOPS if dpd else 0.0)) * pairs_pp / 2.0 + STEP_FLOPS
+        achieved = r["n"] * flops_pp / avg_s / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=traffic,
+                    flops_per_particle=round(flops_pp, 1),
+                    kernel=("k_force<kDpdForce> (LJ + DPD pair terms; the kicks and drift follow in "
+                            "k_integrate), plain steps") if dpd else
+                    "k_force (fused LJ force, Langevin, velocity Verlet), plain steps")
+    roof.update(avg_kernel_us=round(avg_s * 1e6, 3), launches=force_n,
+                hbm_GBs_if_traffic=(round(traffic / avg_s / 1e9, 1) if traffic else None))
+    return roof
+
+
+# ------------------------------------------------------------------ legs
+def viscosity_pair(name, shear_rate, skin, steps=ETA_STEPS, warmup=ETA_WARMUP):
+    """FP64 and mixed runs of the same start, fixed length: eta +- block SE each,
+    their difference in units of the combined error, and the throughputs."""
+    out = {}
+    for prec in ("fp64", "mixed"):
+        x, u, p = workload(name, shear_rate, prec, skin=skin)
+        r = run_gpu(x, u, p, steps, warmup)
+        out[prec] = dict(eta=r["eta"], eta_se=r["eta_se"], value=r["value"],
+                         force_kernel_us=1e3 * r["phases"]["force"][0] / max(r["phases"]["force"][1], 1))
+        log(f"bench: {name} shear_rate={shear_rate} {prec}: eta={r['eta']:.4f} +- {r['eta_se']:.4f} "
+            f"{r['value']:.4e} p-steps/s")
+    a, b = out["fp64"], out["mixed"]
+    out["eta_diff"] = b["eta"] - a["eta"]
+    out["eta_diff_in_se"] = abs(b["eta"] - a["eta"]) / math.hypot(a["eta_se"], b["eta_se"])
+    out["mixed_speedup"] = b["value"] / a["value"]
+    out["window"] = (f"{steps} timed steps after {warmup}, stress every 10 steps, eta over the last "
+                     f"{int(ETA_WINDOW * 100)}% of the samples, standard error of 10 block means")
+    return out
 
 
 def serving_bench(count=64):
@@ -175,62 +302,61 @@ def serving_bench(count=64):
     return out
 
 
-def cpu_baseline(n, shear_rate, nsteps, thermostat="langevin", workload="lj"):
+def host_info():
+    info = dict(nproc=os.cpu_count())
+    try:
+        aff = sorted(os.sched_getaffinity(0))
+        info["affinity"] = f"{len(aff)} cpus: {aff[0]}-{aff[-1]}" if aff else ""
+        info["usable_cpus"] = len(aff)
+    except AttributeError:
+        info["usable_cpus"] = os.cpu_count()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info["OMP_NUM_THREADS"] = os.environ.get("OMP_NUM_THREADS")
+    return info
+
+
+def cpu_runs():
+    """The FP64 cell-list oracle (oracle/) on bounded samples of C1 (LJ N=1000), C2 (LJ
+    N=256,000) and C3 (KG 400,000 beads; the overlap-free lattice-path start, since no
+    oracle input comes from the GPU path), single-threaded and with its OpenMP timing build
+    on every usable core.  ~15-25 s in total."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
-    if workload == "kg":
-        w, p = kg_params(shear_rate, "fp64")
-        what = f"{p.n_chains} x {p.chain_len} Kremer-Grest melt"
-    else:
-        w, p = lj_params(n, shear_rate, "fp64", thermostat=thermostat)
-        what = f"{p.n}-particle LJ system"
-    op = O.make_params(p.n, p.box, shear_rate=p.shear_rate, dt=p.dt, kT=p.kT, gamma=p.gamma,
-                       rc=p.rc, fene_k=p.fene_k, fene_r0=p.fene_r0, seed=p.seed,
-                       chain_len=p.chain_len, n_chains=p.n_chains, thermostat=thermostat)
-    sim = O.Sim(w.x, w.u, op, step0=0, method=1)
-    t0 = time.perf_counter()
-    sim.run(nsteps)
-    t1 = time.perf_counter()
-    return dict(value=p.n * nsteps / (t1 - t0), unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"{nsteps} steps of the same {what} (FP64 cell-list oracle, "
-                       f"1 thread, {t1 - t0:.1f} s)")
-
-
-def kernel_hash():
-    """Hash of the kernel source: le_kernels.hip followed by le_internal.h (its
-    compile-time tile and halo sizes)."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in ("le_kernels.hip", "le_internal.h"):
-        with open(os.path.join(ROOT, "paper_2109_11083_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-def read_traffic(name, skin):
-    """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary
-    (profiles/<name>.md), or None if it was taken on another kernel source or
-    at another skin (other list lengths, other traffic)."""
-    path = os.path.join(ROOT, "profiles", name + ".md")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and line.strip().startswith("- "):
-                k, v = line.strip()[2:].split(":", 1)
-                vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel source sha256 prefix") != kernel_hash():
-        return None
-    try:
-        if abs(float(vals["skin"]) - float(skin)) > 1e-9:
-            return None
-    except (KeyError, ValueError):
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    from paper_2109_11083_amd import inputs
+    hi = host_info()
+    cores = int(os.environ.get("OMP_NUM_THREADS") or hi.get("usable_cpus") or 1)
+    cores = max(1, min(cores, hi.get("usable_cpus") or cores))
+    threads = O.timing_threads(cores)
+    cases = []
+    w1 = inputs.lj_workload(n_side=10, shear_rate=0.1, seed=11)
+    c1 = (w1.x, w1.u, O.make_params(1000, w1.box, shear_rate=0.1, seed=11))
+    x2, u2, p2 = lj_params(256000, 0.1, "fp64")
+    c2 = (x2, u2, O.make_params(p2.n, p2.box, shear_rate=0.1, seed=21))
+    w3 = inputs.kg_workload(KG_CHAINS, KG_LEN, shear_rate=0.01, seed=31, layout="snake")
+    p3 = kg_params(0.01, "fp64")
+    c3 = (w3.x, w3.u, O.make_params(p3.n, p3.box, shear_rate=0.01, dt=0.01, gamma=0.5, rc=p3.rc,
+                                    seed=31, chain_len=KG_LEN, n_chains=KG_CHAINS))
+    plan = [("C1 LJ N=1000", c1, 400, 1000), ("C2 LJ N=256000", c2, 4, 16),
+            ("C3 KG 2000x200", c3, 10, 20)]
+    for name, (x, u, op), n1, nall in plan:
+        for timing, steps in ((False, n1), (True, nall)):
+            sim = O.Sim(x, u, op, step0=0, timing=timing)
+            t0 = time.perf_counter()
+            sim.run(steps)
+            dt = time.perf_counter() - t0
+            n = x.shape[1]
+            cases.append(dict(config=name, threads=threads if timing else 1, steps=steps,
+                              seconds=round(dt, 3), value=n * steps / dt))
+            log(f"bench: cpu oracle {name} {threads if timing else 1} thread(s): {n * steps / dt:.4e} "
+                f"p-steps/s ({steps} steps, {dt:.1f} s)")
+    return dict(host=hi, runs=cases, threads_all=threads)
 
 
 def main():
@@ -238,21 +364,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--shear-rate", type=float, default=None,
-                    help="default 0.1 (LJ) / 0.01 (KG)")
+    ap.add_argument("--shear-rate", type=float, default=None, help="default 0.01 (KG) / 0.1 (LJ)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--n", type=int, default=256000,
                     help="LJ particles: n sites of a ceil(n^(1/3))^3 lattice (256000 -> 64^3)")
-    ap.add_argument("--cpu-steps", type=int, default=None,
-                    help="oracle steps of the CPU baseline (default 12 for LJ, 40 for the KG melt: 10-20 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events in the timed region (then no per-kernel roofline)")
     ap.add_argument("--skin", default="auto",
                     help="neighbour-list skin, or 'auto' (autotuned per workload, short bursts)")
-    ap.add_argument("--workload", default="lj", choices=["lj", "kg"],
-                    help="lj: 256,000-particle LJ fluid (the headline); kg: 2000 x 200 Kremer-Grest melt")
+    ap.add_argument("--workload", default="kg", choices=["kg", "lj"],
+                    help="kg: 2000 x 200 Kremer-Grest melt (the headline); lj: 256,000-particle LJ fluid")
     ap.add_argument("--thermostat", default="langevin", choices=["langevin", "dpd", "langevin_abs"],
                     help="LJ workload: Langevin on the peculiar velocity (gamma 1), DPD (gamma 5) or "
                          "Langevin on the lab velocity (gamma 1)")
@@ -274,111 +397,93 @@ def main():
         return
     kg = args.workload == "kg"
     sr = args.shear_rate if args.shear_rate is not None else (0.01 if kg else 0.1)
-
-    tune_table = None
     th = "langevin" if kg else args.thermostat
     dpd = th == "dpd"
+
+    tune_table = None
     if args.skin == "auto":
-        skin, tune_table = pick_skin(args.n, sr, args.precision, args.workload, thermostat=th)
+        skin, tune_table = pick_skin(args.workload, sr, args.precision, n=args.n, thermostat=th)
         log(f"bench: autotuned skin {skin}: {tune_table}")
     else:
         skin = float(args.skin)
-    args.skin = skin
-    size = f"{KG_CHAINS}x{KG_LEN}" if kg else f"n={args.n}"
-    log(f"bench: {args.workload} {size} shear_rate={sr} {args.precision} "
-        f"steps={args.steps} warmup={args.warmup} skin={skin}")
-    r = run_gpu(args.n, sr, args.precision, args.steps, args.warmup,
-                timing=0 if args.no_timing else TIMING_FORCE, skin=args.skin, workload=args.workload,
-                thermostat=th)
+    x, u, p = workload(args.workload, sr, args.precision, skin=skin, n=args.n, thermostat=th)
+    log(f"bench: {args.workload} n={p.n} shear_rate={sr} {args.precision} steps={args.steps} "
+        f"warmup={args.warmup} skin={skin}")
+    r = run_gpu(x, u, p, args.steps, args.warmup, timing=0 if args.no_timing else TIMING_FORCE)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
-
-    # roofline of the dominant kernel: the fused force / thermostat / integrator
-    # kernel of plain steps (timing phase 0), from its event-timed average over
-    # every 8th launch of the timed region
-    force_ms, force_n = r["phases"]["force"]
-    roofline = None
-    kname = ("k_force_kg400k_" if kg else ("k_force_dpd_lj256k_" if dpd else "k_force_lj256k_")) + args.precision
-    if force_n > 0:
-        avg_s = force_ms / 1e3 / force_n
-        traffic = read_traffic(kname + "_traffic", args.skin)
-        if kg:
-            # HBM-bound: algorithmic bytes of the fused step per particle
-            achieved = r["n"] * BYTES_FUSED / avg_s / 1e9
-            roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
-                            frac=round(achieved / PEAK_HBM_GBS, 5), traffic=traffic,
-                            bytes_per_particle=BYTES_FUSED)
-        else:
-            rho = r["n"] / (r["box"][0] * r["box"][1] * r["box"][2])
-            pairs_pp = 4.0 / 3.0 * math.pi * r["rc"] ** 3 * rho
-            flops_pp = (PAIR_FLOPS + (DPD_PAIR_FLOPS if dpd else 0.0)) * pairs_pp / 2.0 + STEP_FLOPS
-            achieved = r["n"] * flops_pp / avg_s / 1e12
-            roofline = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP64_TFLOPS,
-                            unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 5), traffic=traffic,
-                            flops_per_particle=round(flops_pp, 1))
-        roofline.update(kernel=("k_force<kDpdForce> (LJ + DPD pair terms; the kicks and drift follow in "
-                                "k_integrate), plain steps") if dpd else
-                        "k_force (fused pair force + Langevin + velocity Verlet), plain steps",
-                        avg_kernel_us=round(avg_s * 1e6, 3), launches=force_n,
-                        hbm_GBs_if_traffic=(round(traffic / avg_s / 1e9, 1) if traffic else None))
+    roofline = roofline_of(r, args.workload, args.precision, skin, dpd=dpd)
 
     extra = {}
     # per-phase device time of the same workload (all phases event-timed; a separate, shorter run)
-    b = run_gpu(args.n, sr, args.precision, min(args.steps, 2000), 100, timing=0xF, skin=args.skin,
-                workload=args.workload, thermostat=th)
+    b = run_gpu(x, u, p, 2000, 100, timing=0xF)
     extra["phase_us_per_step"] = {k: round(1e3 * v[0] / b["steps"], 2) for k, v in b["phases"].items()}
+    extra["rebuilds_per_1000_steps_2000_step_run"] = 1000 * b["rebuilds"] / 2000
     log(f"bench: phases {extra['phase_us_per_step']}")
-    if not args.no_extra and not dpd:
-        if not kg:
-            for sr2 in (0.01, 1.0):
-                e = run_gpu(args.n, sr2, args.precision, 2000, 100, skin=args.skin)
-                extra[f"lj_shear_rate_{sr2}"] = dict(value=e["value"],
-                                                    rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
-                                                    eta=e["eta"])
-                log(f"bench: shear_rate={sr2}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
-        # the other precision on the same workload: throughput and viscosity with its error bar
-        other = "mixed" if args.precision == "fp64" else "fp64"
-        m = run_gpu(args.n, sr, other, args.steps, args.warmup, skin=args.skin, workload=args.workload)
-        fm, fn = m["phases"]["force"]
-        extra[f"{args.workload}_{other}"] = dict(
-            value=m["value"], force_kernel_us=1e3 * fm / max(fn, 1), eta=m["eta"], eta_se=m["eta_se"],
-            eta_diff_vs_main=(m["eta"] - r["eta"]) if (r["eta"] is not None and m["eta"] is not None)
-            else None,
-            eta_diff_in_se=(abs(m["eta"] - r["eta"]) / math.hypot(m["eta_se"], r["eta_se"])
-                            if (m["eta_se"] and r["eta_se"]) else None))
-        log(f"bench: {other}: {m['value']:.4e} p-steps/s eta={m['eta']}")
-        if not kg:
-            # Kremer-Grest melt, 2000 chains x 200 beads (HBM-bound pair kernel)
-            kskin, _ = pick_skin(0, 0.01, args.precision, "kg")
-            k = run_gpu(0, 0.01, args.precision, 2000, 100, skin=kskin, workload="kg")
-            kf, kn = k["phases"]["force"]
-            kus = 1e3 * kf / max(kn, 1)
-            extra["kg_2000x200"] = dict(value=k["value"], force_kernel_us=kus,
-                                        force_kernel_GBs_algorithmic=k["n"] * BYTES_FUSED / (kus * 1e-6) / 1e9,
-                                        rebuilds_per_1000=1000 * k["rebuilds"] / 2000, shear_rate=0.01,
-                                        skin=kskin)
-            log(f"bench: kg: {k['value']:.4e} p-steps/s force {kus:.1f} us")
+    viscosity = None
 
-    if args.serve and not kg and th == "langevin":
-        extra["serving"] = serving_bench(args.serve_requests)
+    def guarded(name, fn):
+        """An extra leg; a failure (e.g. a latched device error) is recorded, not fatal."""
+        try:
+            return fn()
+        except Exception as exc:  # noqa: BLE001 - reported in the JSON line
+            log(f"bench: {name} failed: {exc}")
+            return dict(error=str(exc))
+
+    if not args.no_extra and not dpd:
+        if kg:
+            # the 256,000-particle LJ fluid: throughput and force-kernel roofline at its own skin
+            ljskin, ljtable = pick_skin("lj", 0.1, "fp64")
+            x2, u2, p2 = workload("lj", 0.1, "fp64", skin=ljskin)
+            e = run_gpu(x2, u2, p2, 2000, 100)
+            extra["lj_256k"] = dict(value=e["value"], ms_per_step=e["ms_per_step"], skin=ljskin,
+                                    rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
+                                    roofline=roofline_of(e, "lj", "fp64", ljskin), skin_autotune=ljtable)
+            log(f"bench: lj 256k: {e['value']:.4e} p-steps/s")
+        else:
+            ljskin = skin
+        for sr2 in (0.01, 1.0):
+            x2, u2, p2 = workload("lj", sr2, "fp64", skin=ljskin)
+            e = run_gpu(x2, u2, p2, 2000, 100)
+            extra[f"lj_256k_shear_rate_{sr2}"] = dict(value=e["value"],
+                                                     rebuilds_per_1000=1000 * e["rebuilds"] / 2000)
+            log(f"bench: lj shear_rate={sr2}: {e['value']:.4e} p-steps/s rebuilds={e['rebuilds']}")
+        # viscosity in FP64 and mixed precision from fixed-length runs (Eq. viscosity)
+        viscosity = dict(lj_256k_shear_rate_0_1=guarded("lj viscosity", lambda: viscosity_pair("lj", 0.1, ljskin)))
+        kskin = skin if kg else pick_skin("kg", 0.01, "fp64")[0]
+        for sr3 in (0.01, 0.1):
+            viscosity[f"kg_400k_shear_rate_{sr3}"] = guarded(
+                "kg viscosity", lambda: viscosity_pair("kg", sr3, kskin, steps=20000, warmup=1000))
+    if args.serve and not args.no_extra and th == "langevin":
+        extra["serving"] = guarded("serving", lambda: serving_bench(args.serve_requests))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu_steps = args.cpu_steps if args.cpu_steps else (40 if kg else 12)
-        cpu = cpu_baseline(args.n, sr, cpu_steps, thermostat=th, workload=args.workload)
-        log(f"bench: cpu oracle {cpu['value']:.4e} particle-steps/s")
+        runs = cpu_runs()
+        extra["cpu_oracle"] = runs
+        want = "C3 KG 2000x200" if kg else "C2 LJ N=256000"
+        best = [c for c in runs["runs"] if c["config"] == want and c["threads"] == runs["threads_all"]][-1]
+        hi = runs["host"]
+        cpu = dict(value=best["value"], unit="particle-steps/s", cores=best["threads"], kind="oracle",
+                   sample=(f"{best['steps']} steps of the {want} system (FP64 cell-list oracle, OpenMP "
+                           f"timing build, {best['threads']} threads, {best['seconds']:.1f} s; host "
+                           f"{hi.get('model', '?')}, nproc {hi.get('nproc')}, affinity "
+                           f"{hi.get('affinity', '?')}"
+                           + ("; lattice-path start of the same melt" if kg else "") + ")"))
 
     if kg:
-        wl = (f"Kremer-Grest melt {KG_CHAINS} chains x {KG_LEN} beads (N={r['n']}), density 0.85, "
-              f"WCA + FENE(30, 1.5), T=1, Langevin gamma=0.5 on peculiar velocity, shear_rate={sr}, "
-              f"dt=0.01, skin {args.skin}, {args.precision}; overlap-free lattice-path start")
+        info = _KG_WARM[31][2]
+        wl = (f"Kremer-Grest melt {KG_CHAINS} chains x {KG_LEN} beads (N={r['n']}), random walks of "
+              f"bond 0.97, density 0.85, WCA + FENE(30, 1.5), T=1, Langevin gamma=0.5 on peculiar "
+              f"velocity, shear_rate={sr}, dt=0.01, skin {skin}, {args.precision}; warmed up without "
+              f"shear with capped forces ({info.steps} steps, max force {info.max_force:.0f} < 1e3) "
+              f"before the timed region")
     else:
         tdesc = {"langevin": "Langevin gamma=1 on peculiar velocity",
                  "langevin_abs": "Langevin gamma=1 on lab velocity",
                  "dpd": "DPD gamma=5, r_c 2.5"}[th]
         wl = (f"LJ fluid N={r['n']} (64^3 lattice sites, N chosen), density 0.8442, rc 2.5, "
-              f"T=1, {tdesc}, shear_rate={sr}, "
-              f"dt=0.005, skin {args.skin}, {args.precision}")
+              f"T=1, {tdesc}, shear_rate={sr}, dt=0.005, skin {skin}, {args.precision}")
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -398,14 +503,13 @@ def main():
             "shear_rate": sr,
             "precision": args.precision,
             "stress_sample_every": 10,
-            "skin": args.skin,
+            "skin": skin,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
         "rebuilds_per_1000_steps": round(1000.0 * r["rebuilds"] / args.steps, 2),
         "skin_autotune": tune_table,
-        "viscosity": {"eta": r["eta"], "block_se": r["eta_se"],
-                      "window": "second half of the timed steps, 10 blocks"},
+        "viscosity": viscosity,
         "ux_profile_50_bins": [round(v, 5) for v in r["ux_profile"]],
         "kT_kinetic": r["kT"],
         "extra": extra,

@@ -23,6 +23,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     double box[3];      /* L_x (flow), L_y (gradient), L_z (vorticity) */
@@ -436,6 +439,71 @@ static void add_angles(const double *x, double Delta, force_ctx *fc)
         }
 }
 
+#ifdef _OPENMP
+/* Timing build only (gcc -fopenmp, the CPU baseline of the benchmark): the   */
+/* grid loop of O6 split over threads by particle i, each thread summing into */
+/* its own force, virial and energy arrays, which are then added together.    */
+/* The pairs and the force law are those of the serial loop; only the order   */
+/* of the sums differs.  The parity tests use the serial build.              */
+static void grid_forces_parallel(int64_t n, const double *x, double Delta, force_ctx *fc)
+{
+    const orc_params *p = fc->p;
+    orc_grid g;
+    grid_build(&g, n, x, p->box, p->rc);
+    const double rc2 = p->rc * p->rc;
+    const int nth = omp_get_max_threads();
+    double *Fs = (double *)calloc((size_t)nth * 3 * (size_t)n, sizeof(double));
+    double *Ws = (double *)calloc((size_t)nth * 7, sizeof(double));
+#pragma omp parallel
+    {
+        const int t = omp_get_thread_num();
+        force_ctx loc = {p, Fs + (size_t)t * 3 * (size_t)n, fc->W ? Ws + 7 * t : NULL,
+                         fc->e ? Ws + 7 * t + 6 : NULL, n};
+        int64_t *nb = (int64_t *)malloc(sizeof(int64_t) * (size_t)(27 + 18 * g.nc[0] + 16));
+        double d[3];
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t c = g.cell_of[i];
+            int32_t ix = c % g.nc[0];
+            int32_t iy = (c / g.nc[0]) % g.nc[1];
+            int32_t iz = c / (g.nc[0] * g.nc[1]);
+            int m = grid_neighbours(&g, ix, iy, iz, nb);
+            for (int q = 0; q < m; ++q)
+                for (int64_t s = g.start[nb[q]]; s < g.start[nb[q] + 1]; ++s) {
+                    int64_t j = g.list[s];
+                    if (j <= i) continue;
+                    double r2 = orc_disp(x, n, i, j, Delta, p->box, d, NULL);
+                    if (r2 < rc2) lj_pair_cb(&loc, i, j, d, r2);
+                }
+        }
+        free(nb);
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < 3 * n; ++k)
+            for (int u = 0; u < nth; ++u) fc->F[k] += Fs[(size_t)u * 3 * (size_t)n + (size_t)k];
+    }
+    for (int u = 0; u < nth; ++u) {
+        if (fc->W) for (int a = 0; a < 6; ++a) fc->W[a] += Ws[7 * u + a];
+        if (fc->e) *fc->e += Ws[7 * u + 6];
+    }
+    free(Fs);
+    free(Ws);
+    grid_free(&g);
+}
+#endif
+
+/* Threads of the timing build (no effect in the serial build); returns the  */
+/* number in use.                                                            */
+int orc_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
 /* Conservative forces (pairs + bonds) of a configuration, plus the virial   */
 /* W_ab = sum_{i<j} d_a F_ij,b and the potential energy.  method 0: all      */
 /* pairs by brute force; 1: through the grid of O6.  F, W6, energy may be    */
@@ -456,6 +524,10 @@ int orc_forces(int64_t n, const double *x, double Delta, const orc_params *p, in
                 if (r2 < rc2) lj_pair_cb(&fc, i, j, d, r2);
             }
     } else {
+#ifdef _OPENMP
+        if (omp_get_max_threads() > 1) grid_forces_parallel(n, x, Delta, &fc);
+        else
+#endif
         grid_pairs(n, x, Delta, p->box, p->rc, lj_pair_cb, &fc);
     }
     int rc = add_bonds(x, Delta, &fc);
@@ -664,6 +736,9 @@ static void thermostat(int64_t n, const double *x, const double *u, const double
     const double Ly = p->box[1];
     const double pref = sqrt(24.0 * p->gamma * p->mass * p->kT / p->dt);
     const double sr = (p->thermostat == 2 || p->velocity == 1) ? 0.0 : p->shear_rate;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t i = 0; i < n; ++i) {
         double c[3];
         c[0] = u[i] - sr * (x[n + i] - 0.5 * Ly);

@@ -18,20 +18,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "le_oracle.c")
 LIB = os.path.join(HERE, "_build", "liboracle.so")
+LIB_OMP = os.path.join(HERE, "_build", "liboracle_omp.so")  # timing build (CPU baseline only)
 
 PAIR_LJ, PAIR_WCA = 0, 1
 E_BOND, E_NONFINITE = -4, -5
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle into oracle/_build/liboracle.so."""
+    """Compile the oracle into oracle/_build/liboracle.so, and its OpenMP timing
+    build (the CPU baseline's all-cores run) into liboracle_omp.so."""
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
-               "-shared", "-o", tmp, SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, LIB)
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp"
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
+                   *extra, "-shared", "-o", tmp, SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(tmp, out)
     return LIB
 
 
@@ -60,14 +63,34 @@ VELOCITIES = {"lab": 0, "peculiar": 1}
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
+def lib(timing: bool = False):
+    """The serial oracle, or with timing=True its OpenMP timing build (same
+    functions; sums in another order; for the CPU baseline only)."""
+    global _lib, _lib_omp
+    if timing:
+        if _lib_omp is None:
+            lib()
+            _lib_omp = _declare(C.CDLL(LIB_OMP))
+            _lib_omp.orc_threads.argtypes = [C.c_int]
+            _lib_omp.orc_threads.restype = C.c_int
+        return _lib_omp
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not all(os.path.exists(f) and os.path.getmtime(f) >= os.path.getmtime(SRC) for f in (LIB, LIB_OMP)):
             build(force=True)
-        L = C.CDLL(LIB)
+        _lib = _declare(C.CDLL(LIB))
+    return _lib
+
+
+def timing_threads(n: int = 0) -> int:
+    """Set (n > 0) and return the thread count of the timing build."""
+    return lib(timing=True).orc_threads(int(n))
+
+
+def _declare(L):
+    if True:
         dp = C.POINTER(C.c_double)
         i64p = C.POINTER(C.c_int64)
         i32p = C.POINTER(C.c_int32)
@@ -113,8 +136,7 @@ def lib():
         L.orc_observables.restype = None
         L.orc_energy.argtypes = [C.c_int64, dp, C.c_double, pp, dp]
         L.orc_energy.restype = C.c_int
-        _lib = L
-    return _lib
+    return L
 
 
 def _dp(a):
@@ -316,15 +338,16 @@ def msd(unw, ref):
 class Sim:
     """A running oracle simulation (state in tag order, wrapped every step)."""
 
-    def __init__(self, x0, u0, p: Params, step0=0, method=1):
+    def __init__(self, x0, u0, p: Params, step0=0, method=1, timing=False):
         self.p = p
         self.method = method
+        self.L = lib(timing)
         self.x = _c64(x0).copy()
         self.u = _c64(u0).copy()
         self.n = self.x.shape[1]
         self.F = np.zeros_like(self.x)
         self.step = int(step0)
-        rc = lib().orc_init(self.n, _dp(self.x), _dp(self.u), _dp(self.F), self.step, C.byref(p),
+        rc = self.L.orc_init(self.n, _dp(self.x), _dp(self.u), _dp(self.F), self.step, C.byref(p),
                             method)
         if rc != 0:
             raise OracleError(rc)
@@ -338,7 +361,7 @@ class Sim:
         ns = nsteps // sample_every if sample_every > 0 else 0
         out = np.zeros((max(ns, 1), 6))
         st = C.c_int64(self.step)
-        rc = lib().orc_run(self.n, _dp(self.x), _dp(self.u), _dp(self.F), C.byref(st), C.byref(self.p),
+        rc = self.L.orc_run(self.n, _dp(self.x), _dp(self.u), _dp(self.F), C.byref(st), C.byref(self.p),
                            self.method, int(nsteps), int(sample_every), _dp(out))
         self.step = st.value
         if rc != 0:
