@@ -190,6 +190,26 @@ le_status le_forces(le_sim* s, double* f_out, double* virial6);
 le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
                   int64_t ring_cap);
 
+/* Batched stepping (the same velocity-Verlet steps as le_step, Section 2.2,
+ * for many independent simulations at once): advances every simulation of
+ * sims[0..nsims) by nsteps.  Each kernel of a step is launched once for all
+ * members of one kernel configuration (precision, pair layout, bonds,
+ * thermostat kind), its grid covering the blocks of every member, so the
+ * launch count per step does not grow with nsims; members may differ in N,
+ * box, shear rate, skin, seed and every other parameter.  Each member's
+ * arithmetic is exactly that of le_step on it alone, so its results are
+ * bitwise the same alone and in any batch.
+ *   All members must share one stream (the one given to their le_init);
+ *   a null, repeated or foreign-stream entry is LE_E_ARG.
+ *   sample_every > 0: the stress tensor of every sample_every-th new state of
+ *   member k goes to stress_rings[k][(j mod ring_cap)][6], j counted within
+ *   this call (stress_rings: host array of nsims device pointers).
+ *   A member with a latched error (seen by a synchronising call) is skipped;
+ *   one that latches during the call stops on the device, the others go on.
+ *   Per-member errors are reported by le_sync on that member.  Asynchronous. */
+le_status le_step_batch(le_sim* const* sims, int32_t nsims, int64_t nsteps, int32_t sample_every,
+                        double* const* stress_rings, int64_t ring_cap);
+
 /* Stress of the current state (Eq. tensor): sigma_ab = -(1/V)[sum_i m c_a c_b
  * + sum_{i<j} d_a F_ij,b] with peculiar velocities c (Eq. vi) and
  * conservative forces only; order xx, yy, zz, xy, xz, yz.  The viscosity of
@@ -245,6 +265,15 @@ le_status le_get_state(le_sim* s, double* x, double* u, double* f, int64_t* step
  * legacy default stream (null), which cannot be captured. */
 le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, double* stress_ring,
                           int64_t ring_cap, le_graph** out);
+
+/* A HIP graph of le_step_batch(sims, nsims, nsteps, sample_every,
+ * stress_rings, ring_cap), captured once on the members' common stream (one
+ * host launch per chunk of steps for the whole batch).  nsteps must be even;
+ * replays advance every member as that call would.  The graph is owned by
+ * the caller (le_graph_destroy) and must not outlive any member.  LE_E_STATE
+ * on the legacy default stream or when every member has a latched error. */
+le_status le_batch_graph_create(le_sim* const* sims, int32_t nsims, int64_t nsteps, int32_t sample_every,
+                                double* const* stress_rings, int64_t ring_cap, le_graph** out);
 
 /* Enqueue one replay on the simulation's stream.  Eager calls may be mixed
  * with replays (e.g. le_get_state, odd le_step counts): the device control

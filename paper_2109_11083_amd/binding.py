@@ -36,7 +36,8 @@ EXPORTED = [
     "le_workspace_bytes", "le_init", "le_build_cells", "le_forces", "le_step", "le_stress",
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
     "le_timing_enable", "le_timing_read", "le_observables", "le_graph_create", "le_graph_launch",
-    "le_graph_destroy", "le_unwrapped", "le_msd", "le_forces_static",
+    "le_graph_destroy", "le_unwrapped", "le_msd", "le_forces_static", "le_step_batch",
+    "le_batch_graph_create",
 ]
 LE_MAX_BINS = 256
 
@@ -116,6 +117,8 @@ def lib() -> C.CDLL:
     L.le_unwrapped.argtypes = [vp, vp]
     L.le_msd.argtypes = [vp, vp, vp]
     L.le_forces_static.argtypes = [P, vp, vp, vp, vp, i64, vp]
+    L.le_step_batch.argtypes = [C.POINTER(vp), i32, i64, i32, C.POINTER(vp), i64]
+    L.le_batch_graph_create.argtypes = [C.POINTER(vp), i32, i64, i32, C.POINTER(vp), i64, sim_pp]
     for name in EXPORTED:
         if name != "le_strerror":
             getattr(L, name).restype = i32
@@ -164,6 +167,30 @@ def le_forces(sim: int, f_out: int | None, virial6: int | None) -> None:
 def le_step(sim: int, nsteps: int, sample_every: int = 0, stress_ring: int | None = None,
             ring_cap: int = 0) -> None:
     check(lib().le_step(sim, nsteps, sample_every, stress_ring, ring_cap), "le_step")
+
+
+def _ptr_array(ptrs):
+    arr = (C.c_void_p * max(len(ptrs), 1))()
+    for k, v in enumerate(ptrs):
+        arr[k] = v
+    return arr
+
+
+def le_step_batch(sims, nsteps: int, sample_every: int = 0, stress_rings=None, ring_cap: int = 0) -> None:
+    """sims: handles; stress_rings: device pointers (one per simulation) or None."""
+    hs = _ptr_array(list(sims))
+    rings = _ptr_array(list(stress_rings)) if stress_rings is not None else None
+    check(lib().le_step_batch(hs, len(sims), nsteps, sample_every, rings, ring_cap), "le_step_batch")
+
+
+def le_batch_graph_create(sims, nsteps: int, sample_every: int = 0, stress_rings=None,
+                          ring_cap: int = 0) -> int:
+    hs = _ptr_array(list(sims))
+    rings = _ptr_array(list(stress_rings)) if stress_rings is not None else None
+    g = C.c_void_p(0)
+    check(lib().le_batch_graph_create(hs, len(sims), nsteps, sample_every, rings, ring_cap, C.byref(g)),
+          "le_batch_graph_create")
+    return g.value
 
 
 def le_stress(sim: int, sigma6: int) -> None:

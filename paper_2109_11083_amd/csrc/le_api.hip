@@ -13,10 +13,11 @@
 using namespace le;
 
 struct le_graph {
-  le_sim* s;
+  hipStream_t stream;
   hipGraph_t graph;
   hipGraphExec_t exec;
-  Ctrl* ctrl_at;   // control copy current when the graph starts
+  std::vector<le_sim*> sims;  // the simulations it advances (one, or a batch)
+  std::vector<Ctrl*> ctrl_at; // each one's control copy current when the graph starts
 };
 
 struct le_sim {
@@ -26,6 +27,7 @@ struct le_sim {
   int32_t host_status;                 // last status seen by a synchronising call
   Ctrl* ctrl_base;                     // the two control copies; d.ctrl is the current one
   unsigned long long* vmax_base;       // the two speed-bound slot arrays (d.vmax current)
+  Dev* dev_dev;                         // device copies of d for the two control copies (batched launches)
   unsigned long long* counter;         // device scratch counter (pairs_out)
   double* scratch6;                    // device 6 doubles
   // phase timing (le_timing_enable)
@@ -162,6 +164,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
                              sizeof(double));
   unsigned long long* counter = (unsigned long long*)take(sizeof(unsigned long long));
   double* scratch6 = (double*)take(6 * sizeof(double));
+  Dev* dev_dev = (Dev*)take(2 * sizeof(Dev));
   if (d) {
     // copy buffer pointers into d (geometry fields are filled by the caller)
     d->ctrl = t.ctrl;
@@ -181,7 +184,13 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     d->partials = t.partials;
     d->obs_part = t.obs_part;
   }
-  if (s) { s->counter = counter; s->scratch6 = scratch6; s->ctrl_base = t.ctrl; s->vmax_base = t.vmax; }
+  if (s) {
+    s->counter = counter;
+    s->scratch6 = scratch6;
+    s->ctrl_base = t.ctrl;
+    s->vmax_base = t.vmax;
+    s->dev_dev = dev_dev;
+  }
   return off + kAlign;  // room to align the caller's base pointer
 }
 
@@ -355,6 +364,129 @@ static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Batched stepping: simulations that share a kernel configuration form a
+// group; each step launches every kernel once per group (at most kMaxBatch
+// simulations per launch), the blocks of all members in one grid.
+
+struct BatchGroup {
+  Dev cfg;                     // host descriptor of the first member (kernel configuration)
+  std::vector<le_sim*> sims;
+  Batch par[2], scan[2], tile[2], one[2];  // [v]: v = 0 descriptors of the copies current at the call
+};
+
+bool same_config(const Dev& a, const Dev& b) {
+  return a.staged == b.staged && a.small_halo == b.small_halo && a.precision == b.precision &&
+         (a.chain_len > 0) == (b.chain_len > 0) && (a.force_cap > 0.0) == (b.force_cap > 0.0) &&
+         (a.thermostat == LE_THERMO_DPD) == (b.thermostat == LE_THERMO_DPD);
+}
+
+void fill_group(BatchGroup& g) {
+  for (int v = 0; v < 2; ++v) {
+    Batch* bs[4] = {&g.par[v], &g.scan[v], &g.tile[v], &g.one[v]};
+    for (Batch* b : bs) {
+      memset(b, 0, sizeof(Batch));
+      b->nsims = (int32_t)g.sims.size();
+    }
+    int32_t op = 0, os = 0, ot = 0;
+    for (size_t k = 0; k < g.sims.size(); ++k) {
+      le_sim* s = g.sims[k];
+      const int cur = s->d.ctrl == s->ctrl_base ? 0 : 1;
+      const Dev* dv = s->dev_dev + (cur ^ v);
+      g.par[v].start[k] = op; g.scan[v].start[k] = os; g.tile[v].start[k] = ot; g.one[v].start[k] = (int32_t)k;
+      g.par[v].dev[k] = g.scan[v].dev[k] = g.tile[v].dev[k] = g.one[v].dev[k] = dv;
+      op += (s->d.n + kBlock - 1) / kBlock;
+      os += (s->d.ncell + kScanTile - 1) / kScanTile;
+      ot += s->d.ntiles;
+    }
+    const size_t m = g.sims.size();
+    g.par[v].start[m] = op; g.scan[v].start[m] = os; g.tile[v].start[m] = ot; g.one[v].start[m] = (int32_t)m;
+  }
+}
+
+// Group the simulations (at most kMaxBatch per group).  LE_E_ARG for a null,
+// repeated or foreign-stream simulation.
+le_status plan_batch(le_sim* const* sims, int32_t nsims, std::vector<BatchGroup>& groups) {
+  if (!sims || nsims < 1) return LE_E_ARG;
+  for (int32_t a = 0; a < nsims; ++a) {
+    if (!sims[a] || sims[a]->stream != sims[0]->stream) return LE_E_ARG;
+    for (int32_t b = 0; b < a; ++b)
+      if (sims[b] == sims[a]) return LE_E_ARG;
+  }
+  for (int32_t a = 0; a < nsims; ++a) {
+    le_sim* s = sims[a];
+    if (s->host_status) continue;  // latched: its kernels would be no-ops anyway
+    BatchGroup* g = nullptr;
+    for (BatchGroup& c : groups)
+      if (c.sims.size() < (size_t)kMaxBatch && same_config(c.cfg, s->d)) { g = &c; break; }
+    if (!g) {
+      groups.emplace_back();
+      g = &groups.back();
+      g->cfg = s->d;
+    }
+    g->sims.push_back(s);
+  }
+  for (BatchGroup& g : groups) fill_group(g);
+  return LE_OK;
+}
+
+le_status step_batch(std::vector<BatchGroup>& groups, hipStream_t q, int64_t nsteps, int32_t sample_every,
+                     double* const* rings, int64_t ring_cap, le_sim* const* order, int32_t norder) {
+  // ring of each member: the caller's rings are indexed like `order`
+  auto ring_of = [&](le_sim* s) -> double* {
+    for (int32_t k = 0; k < norder; ++k)
+      if (order[k] == s) return rings[k];
+    return nullptr;
+  };
+  int v = 0;  // which descriptor set is current
+  le_status st = LE_OK;
+  for (BatchGroup& g : groups)
+    if (st == LE_OK) st = hip_check(launch_kick_drift_b(g.par[v], q));
+  for (BatchGroup& g : groups)
+    if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.par[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+  v ^= 1;
+  int64_t ns = 0;
+  for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
+    const bool last = (k == nsteps);
+    const bool sample = sample_every > 0 && (k % sample_every) == 0;
+    for (BatchGroup& g : groups) {
+      if (st != LE_OK) break;
+      if (g.cfg.thermostat == LE_THERMO_DPD) {
+        st = hip_check(launch_force_b(g.tile[v], g.par[v], g.cfg, q, kDpdForce, sample));
+        if (st == LE_OK) st = hip_check(launch_integrate_b(g.tile[v], q, last, sample));
+      } else {
+        st = hip_check(launch_force_b(g.tile[v], g.par[v], g.cfg, q, last ? kStepLast : kStepFused, sample));
+      }
+      if (st == LE_OK && sample) {
+        BatchOut out;
+        memset(&out, 0, sizeof(out));
+        for (size_t m = 0; m < g.sims.size(); ++m) out.ptr[m] = ring_of(g.sims[m]) + 6 * (ns % ring_cap);
+        st = hip_check(launch_stress_final_b(g.one[v], out, q));
+      }
+    }
+    if (sample) ++ns;
+    if (st == LE_OK && !last) {
+      for (BatchGroup& g : groups)
+        if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.par[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+      v ^= 1;
+    }
+  }
+  // every member's control copy alternated once per rebuild test (nsteps times)
+  if (nsteps & 1)
+    for (BatchGroup& g : groups)
+      for (le_sim* s : g.sims) {
+        const bool first = s->d.ctrl == s->ctrl_base;
+        s->d.ctrl = first ? s->ctrl_base + 1 : s->ctrl_base;
+        s->d.vmax = s->vmax_base + (first ? kSlots * kLineU64 : 0);
+      }
+  return st;
+}
+
+}  // namespace
+
+
+namespace {
+
 // Device address of `scratch` on the current device (looked up on the first
 // call made with that device current).
 le_status scratch_addr(void** out) {
@@ -409,6 +541,15 @@ le_status le_init(const le_params* p, const double* x0, const double* u0, const 
   fill_geometry(p, g, &s->d);
   double Delta0 = le_offset(step0, p->dt, s->d.sv, p->box[0]);
   st = hip_check(launch_load_state(s->d, s->stream, x0, u0, f0, step0, Delta0));
+  if (st == LE_OK) {
+    // the descriptors of batched launches: one per control copy
+    Dev a = s->d, b = s->d;
+    a.ctrl = s->ctrl_base; a.ctrl_other = s->ctrl_base + 1;
+    a.vmax = s->vmax_base; a.vmax_other = s->vmax_base + kSlots * kLineU64;
+    b.ctrl = a.ctrl_other; b.ctrl_other = a.ctrl;
+    b.vmax = a.vmax_other; b.vmax_other = a.vmax;
+    st = hip_check(launch_store_dev(a, b, s->dev_dev, s->stream));
+  }
   if (st == LE_OK) st = rebuild(s, true, false);
   if (st == LE_OK && !f0)
     st = hip_check(launch_force(s->d, s->stream, s->d.thermostat == LE_THERMO_DPD ? kDpdForce : kInitForce,
@@ -519,6 +660,60 @@ le_status le_step(le_sim* s, int64_t nsteps, int32_t sample_every, double* stres
   return st;
 }
 
+le_status le_step_batch(le_sim* const* sims, int32_t nsims, int64_t nsteps, int32_t sample_every,
+                        double* const* stress_rings, int64_t ring_cap) {
+  if (nsteps < 0) return LE_E_ARG;
+  if (sample_every > 0 && (!stress_rings || ring_cap <= 0)) return LE_E_ARG;
+  std::vector<BatchGroup> groups;
+  le_status st = plan_batch(sims, nsims, groups);
+  if (st != LE_OK) return st;
+  if (sample_every > 0)
+    for (int32_t k = 0; k < nsims; ++k)
+      if (!stress_rings[k]) return LE_E_ARG;
+  if (nsteps == 0 || groups.empty()) return LE_OK;
+  return step_batch(groups, sims[0]->stream, nsteps, sample_every, stress_rings, ring_cap, sims, nsims);
+}
+
+le_status le_batch_graph_create(le_sim* const* sims, int32_t nsims, int64_t nsteps, int32_t sample_every,
+                                double* const* stress_rings, int64_t ring_cap, le_graph** out) {
+  if (!out || nsteps <= 0 || (nsteps & 1)) return LE_E_ARG;
+  *out = nullptr;
+  if (sample_every > 0 && (!stress_rings || ring_cap <= 0)) return LE_E_ARG;
+  std::vector<BatchGroup> groups;
+  le_status st = plan_batch(sims, nsims, groups);
+  if (st != LE_OK) return st;
+  if (groups.empty()) return LE_E_STATE;
+  if (sample_every > 0)
+    for (int32_t k = 0; k < nsims; ++k)
+      if (!stress_rings[k]) return LE_E_ARG;
+  hipStream_t q = sims[0]->stream;
+  if (!q) return LE_E_STATE;  // the legacy default stream cannot be captured
+  le_graph* g = new (std::nothrow) le_graph();
+  if (!g) return LE_E_ARG;
+  g->stream = q;
+  for (BatchGroup& b : groups)
+    for (le_sim* s : b.sims) {
+      g->sims.push_back(s);
+      g->ctrl_at.push_back(s->d.ctrl);
+    }
+  st = hip_check(hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal));
+  if (st == LE_OK) {
+    le_status st_step = step_batch(groups, q, nsteps, sample_every, stress_rings, ring_cap, sims, nsims);
+    le_status st_end = hip_check(hipStreamEndCapture(q, &g->graph));
+    st = st_step != LE_OK ? st_step : st_end;
+  }
+  for (size_t k = 0; k < g->sims.size() && st == LE_OK; ++k)
+    if (g->sims[k]->d.ctrl != g->ctrl_at[k]) st = LE_E_STATE;  // cannot happen for even nsteps
+  if (st == LE_OK) st = hip_check(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  if (st != LE_OK) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return LE_OK;
+}
+
 le_status le_observables(le_sim* s, int32_t nbins, double* out) {
   if (!s || !out || nbins < 1 || nbins > LE_MAX_BINS) return LE_E_ARG;
   if (s->host_status) return s->host_status;
@@ -566,8 +761,9 @@ le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, doubl
   if (s->host_status) return s->host_status;
   le_graph* g = new (std::nothrow) le_graph();
   if (!g) return LE_E_ARG;
-  g->s = s;
-  g->ctrl_at = s->d.ctrl;
+  g->stream = s->stream;
+  g->sims.push_back(s);
+  g->ctrl_at.push_back(s->d.ctrl);
   const int32_t timing = s->timing;
   s->timing = 0;
   le_status st = hip_check(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
@@ -577,7 +773,7 @@ le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, doubl
     st = st_step != LE_OK ? st_step : st_end;
   }
   s->timing = timing;
-  if (st == LE_OK && s->d.ctrl != g->ctrl_at) st = LE_E_STATE;  // cannot happen for even nsteps
+  if (st == LE_OK && s->d.ctrl != g->ctrl_at[0]) st = LE_E_STATE;  // cannot happen for even nsteps
   if (st == LE_OK) st = hip_check(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
   if (st != LE_OK) {
     if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -590,19 +786,21 @@ le_status le_graph_create(le_sim* s, int64_t nsteps, int32_t sample_every, doubl
 
 le_status le_graph_launch(le_graph* g) {
   if (!g) return LE_E_ARG;
-  le_sim* s = g->s;
-  if (s->host_status) return s->host_status;
-  if (s->d.ctrl != g->ctrl_at) {
-    // an odd number of control updates since the capture: move the state to
-    // the copy the graph reads (the simulation is unchanged)
-    const bool first = g->ctrl_at == s->ctrl_base;
-    unsigned long long* vat = s->vmax_base + (first ? 0 : kSlots * kLineU64);
-    le_status st = hip_check(launch_ctrl_copy(s->d.ctrl, g->ctrl_at, s->d.vmax, vat, s->stream));
-    if (st != LE_OK) return st;
-    s->d.ctrl = g->ctrl_at;
-    s->d.vmax = vat;
+  if (g->sims.size() == 1 && g->sims[0]->host_status) return g->sims[0]->host_status;
+  for (size_t k = 0; k < g->sims.size(); ++k) {
+    le_sim* s = g->sims[k];
+    if (s->d.ctrl != g->ctrl_at[k]) {
+      // an odd number of control updates since the capture: move the state to
+      // the copy the graph reads (the simulation is unchanged)
+      const bool first = g->ctrl_at[k] == s->ctrl_base;
+      unsigned long long* vat = s->vmax_base + (first ? 0 : kSlots * kLineU64);
+      le_status st = hip_check(launch_ctrl_copy(s->d.ctrl, g->ctrl_at[k], s->d.vmax, vat, s->stream));
+      if (st != LE_OK) return st;
+      s->d.ctrl = g->ctrl_at[k];
+      s->d.vmax = vat;
+    }
   }
-  return hip_check(hipGraphLaunch(g->exec, s->stream));
+  return hip_check(hipGraphLaunch(g->exec, g->stream));
 }
 
 le_status le_graph_destroy(le_graph* g) {

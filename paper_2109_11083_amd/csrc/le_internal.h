@@ -131,11 +131,26 @@ struct Dev {
   double* partials;                // [nblocks][kStressComps] (nblocks = ntiles)
   double* obs_part;                // [ceil(n / kBlock)][3 * LE_MAX_BINS + 4] observable partials
   Ctrl* ctrl;                      // current control copy (see Ctrl)
+  Ctrl* ctrl_other;                // the other control copy (written by a batched rebuild test)
   // running max of |c|^2 of the last drift (bits of doubles >= 0) in kSlots
   // words of kLineU64 stride; two arrays alternate with the control copies
   unsigned long long* vmax;
+  unsigned long long* vmax_other;  // the speed-bound slots paired with ctrl_other
   unsigned long long* scan_status; // [ceil(ncell / kScanTile)] look-back words of the cell scan
   Flags* flags;
+};
+
+// Descriptor table of a batched launch: simulation k owns the blocks
+// [start[k], start[k+1]) of the grid and reads its descriptor (a Dev kept in
+// its own workspace, one per control copy) through dev[k].  Passed by value.
+constexpr int kMaxBatch = 64;
+struct Batch {
+  int32_t nsims;
+  int32_t start[kMaxBatch + 1];
+  const Dev* dev[kMaxBatch];
+};
+struct BatchOut {
+  double* ptr[kMaxBatch];  // per-simulation output (the stress sample of this step)
 };
 
 // Image code of an imaged neighbour: sx in [-3, 3], sy and sz in [-1, 1].
@@ -177,6 +192,21 @@ hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t
 hipError_t launch_load_state(const Dev& d, hipStream_t s, const double* x0, const double* u0,
                              const double* f0, int64_t step0, double Delta0);
 hipError_t launch_status_out(const Dev& d, hipStream_t s, int32_t* out);
+
+// Batched launchers: one launch over the blocks of every simulation of a
+// batch (all of one kernel configuration, given by `cfg`, the host copy of any
+// member's descriptor).  Batches by block kind: `par` one block per kBlock
+// particles, `scan` one per kScanTile cells, `tile` one per kTile particles,
+// `one` one block per simulation; `cur` and `nxt` name the descriptors of the
+// current and the other control copy.
+hipError_t launch_store_dev(const Dev& a, const Dev& b, Dev* dst, hipStream_t s);
+hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s);
+hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& par_nxt,
+                            const Batch& tile_nxt, const Dev& cfg, hipStream_t s);
+hipError_t launch_force_b(const Batch& tile_cur, const Batch& par_cur, const Dev& cfg, hipStream_t s,
+                          ForceMode mode, bool sample);
+hipError_t launch_integrate_b(const Batch& tile_cur, hipStream_t s, bool last, bool sample);
+hipError_t launch_stress_final_b(const Batch& one_cur, const BatchOut& out, hipStream_t s);
 hipError_t launch_offsets(double sr, double Lx, double Ly, double dt, int64_t step0, int64_t count,
                           double* out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,

@@ -21,15 +21,28 @@
 namespace le {
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int xcd_block(int nblocks) {
+__device__ __forceinline__ int xcd_map(int b, int nblocks) {
   // Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD works
   // on one contiguous range of cell-sorted particles (its L2 then holds that
   // region's neighbour positions).
   const int X = 8;
-  int b = blockIdx.x;
   int q = nblocks / X, r = nblocks % X;
   int x = b % X, k = b / X;
   return x * q + (x < r ? x : r) + k;
+}
+__device__ __forceinline__ int xcd_block(int nblocks) { return xcd_map((int)blockIdx.x, nblocks); }
+
+// Simulation and local block of global block g of a batched launch: the last
+// simulation whose first block is at or before g (simulations without blocks
+// are skipped).  Uniform across the block.
+__device__ __forceinline__ void locate(const Batch& b, int g, int& sim, int& bid) {
+  int lo = 0, hi = b.nsims - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.start[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  sim = lo;
+  bid = g - b.start[lo];
 }
 
 __device__ __forceinline__ void latch(Flags* f, int32_t st) { atomicCAS(&f->status, 0, st); }
@@ -189,9 +202,9 @@ __device__ __forceinline__ bool rebuild_off(const Dev& d) {
 // boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
 // x and z in place, then each particle's cell and its arrival rank there.
 // Runs of equal cells within a wave take one atomic per run.
-__global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict__ next,
-                                                        unsigned long long* __restrict__ next_vmax,
-                                                        int force, int control) {
+__device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict__ next,
+                                                 unsigned long long* __restrict__ next_vmax, int force,
+                                                 int control, int bid) {
   __shared__ Ctrl sc;
   __shared__ int go;
   if (threadIdx.x < 64) {
@@ -209,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
       sc = c;  // buffers and offset of the state being binned
       go = rb ? 1 : 0;
     }
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
       if (threadIdx.x < kSlots) next_vmax[threadIdx.x * kLineU64] = 0ull;
       if (rb) {
         for (int k = threadIdx.x; k < kSlots * kLineInts; k += 64) d.flags->max_nb_slot[k] = 0;
@@ -226,7 +239,7 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
   }
   __syncthreads();
   if (!go) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bid * kBlock + threadIdx.x;
   const int np = d.np;
   int cell = -1;
   if (i < d.n) {
@@ -277,6 +290,21 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict__ next,
+                                                        unsigned long long* __restrict__ next_vmax,
+                                                        int force, int control) {
+  control_bin_body(d, next, next_vmax, force, control, blockIdx.x);
+}
+
+// Batched form: every simulation advances its step (control) and writes its
+// other control copy (named by its descriptor).
+__global__ void __launch_bounds__(kBlock) k_control_bin_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  const Dev& d = *b.dev[sm];
+  control_bin_body(d, d.ctrl_other, d.vmax_other, 0, 1, bid);
+}
+
 // (2) Exclusive scan of the cell counts into cell_start, one pass with
 // decoupled look-back: block b scans kScanTile cells (8 consecutive per
 // thread), publishes its total in status word b (flag 1), adds the totals of
@@ -291,12 +319,11 @@ __device__ __forceinline__ unsigned long long scan_word(int flag, long long v) {
   return ((unsigned long long)flag << 62) | (unsigned long long)v;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) {
+__device__ __forceinline__ void cell_scan_body(const Dev& d, int b) {
   if (rebuild_off(d)) return;
   __shared__ int wsum[kScanBlock / 64];
   __shared__ long long base_sh;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int b = blockIdx.x;
   const int c0 = b * kScanTile + 8 * threadIdx.x;
   int v[8];
 #pragma unroll
@@ -370,13 +397,24 @@ __global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) {
   if (b == 0 && threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
 }
 
+__global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) { cell_scan_body(d, blockIdx.x); }
+
+// Batched form: the blocks of one simulation are consecutive in the grid, so
+// every block's predecessors were dispatched before it (the look-back waits
+// only on them).
+__global__ void __launch_bounds__(kScanBlock) k_cell_scan_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  cell_scan_body(*b.dev[sm], bid);
+}
+
 // (3) Final slot = cell start + number of cell-mates with a smaller tag, so
 // the order is (cell, tag) whatever the arrival order; copy the particle's
 // state to the other buffers at that slot.
-__global__ void __launch_bounds__(kBlock) k_permute(Dev d) {
+__device__ __forceinline__ void permute_body(const Dev& d, int bid) {
   if (rebuild_off(d)) return;
   const Ctrl* c = d.ctrl;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bid * kBlock + threadIdx.x;
   if (i >= d.n) return;
   const int np = d.np;
   const int pd = c->pos_cur, ad = c->aux_cur;  // destination buffers
@@ -396,6 +434,14 @@ __global__ void __launch_bounds__(kBlock) k_permute(Dev d) {
   }
   d.tag[ad][ns] = t;
   d.slot_of_tag[t] = ns;
+}
+
+__global__ void __launch_bounds__(kBlock) k_permute(Dev d) { permute_body(d, blockIdx.x); }
+
+__global__ void __launch_bounds__(kBlock) k_permute_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  permute_body(*b.dev[sm], bid);
 }
 
 // Neighbour lists of radius r_list through the Lees-Edwards cell stencil.
@@ -483,7 +529,7 @@ __device__ __forceinline__ bool in_list_exact(const Dev& d, double4 pi, double4 
 // each (dy, dz) range in two and write two sub-lists, which the force kernel
 // reads as one sequence of batches.
 template <int HALO, bool GL>
-__global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
+__device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   // staged positions: floats relative to the tile's first particle, image
   // added (8 spare entries: a batch may read up to 7 past the halo)
   __shared__ float hx[HALO + 8], hy[HALO + 8], hz[HALO + 8];
@@ -511,7 +557,6 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   __syncthreads();
   if (skip) return;
   const int np = d.np, np2 = d.np2, K = d.K, n = d.n;
-  const int tile = xcd_block(d.ntiles);
   const int s0 = tile * kTile;
   const int half = (int)(threadIdx.x / kTile);
   const int tl = (int)threadIdx.x - half * kTile;
@@ -828,7 +873,7 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
     __syncthreads();
     if (threadIdx.x == 0) {
       for (int w = 1; w < 2 * kTile / 64; ++w) mx = max(mx, wmax[w]);
-      atomicMax(&d.flags->max_nb_slot[(blockIdx.x % kSlots) * kLineInts], mx);
+      atomicMax(&d.flags->max_nb_slot[(tile % kSlots) * kLineInts], mx);
     }
   }
   if (!valid) return;
@@ -862,6 +907,20 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
     d.bond[i] = lo;
     d.bond[np + i] = hi;
   }
+}
+
+template <int HALO, bool GL>
+__global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
+  neighbors_body<HALO, GL>(d, xcd_block(d.ntiles));
+}
+
+// Batched form: the XCD remap runs over the whole grid (each XCD takes a
+// contiguous range of tiles across the simulations), then the tile is located.
+template <int HALO, bool GL>
+__global__ void __launch_bounds__(2 * kTile) k_neighbors_b(Batch b) {
+  int sm, tile;
+  locate(b, xcd_map((int)blockIdx.x, (int)gridDim.x), sm, tile);
+  neighbors_body<HALO, GL>(*b.dev[sm], tile);
 }
 
 // ---------------------------------------------------------- integrator
@@ -914,13 +973,13 @@ __device__ void reduce_partials(const Dev& d, double* out6, bool virial_only) {
 // First half-kick and drift from a state with full-step velocities:
 // u += dt/(2m) F ; x_new = x + dt u (into the other position buffer).  The
 // step is advanced by the next control kernel.
-__global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
+__device__ __forceinline__ void kick_drift_body(const Dev& d, int bid) {
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = bid * kBlock + threadIdx.x;
   const int np = d.np;
   double v2 = 0.0;
   if (i < d.n) {
@@ -942,7 +1001,15 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) {
     reinterpret_cast<double4*>(d.pos[1 - pc])[i] = q;
     if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) latch(d.flags, LE_E_NONFINITE);
   }
-  vmax_commit<kBlock>(d, v2, blockIdx.x);
+  vmax_commit<kBlock>(d, v2, bid);
+}
+
+__global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) { kick_drift_body(d, blockIdx.x); }
+
+__global__ void __launch_bounds__(kBlock) k_kick_drift_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  kick_drift_body(*b.dev[sm], bid);
 }
 
 // ---------------------------------------------------------- force kernel
@@ -1087,9 +1154,8 @@ __device__ __forceinline__ void block_partials(double* vals, double* out, int lb
 // through LDS before the epilogue.  Without the halo the launch bound of four
 // tiles per block makes the compiler keep fewer registers (more waves; DPD
 // 138 -> 132 us); the launch itself uses one tile.
-template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
-__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force(Dev d, double* __restrict__ f_out,
-                                                     double* __restrict__ sample_out) {
+template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP>
+__device__ __forceinline__ void force_body(const Dev& d, const int lb, double* __restrict__ f_out) {
   static_assert(!CAP || (!STAGED && !MIXED && MODE != kDpdForce), "capped forces: FP64, global layout");
   constexpr bool VIR = SAMPLE || (MODE == kForcesOnly);
   constexpr bool DPD = MODE == kDpdForce;
@@ -1106,7 +1172,6 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_forc
   if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
-  const int lb = xcd_block(d.ntiles);
   const int half = STAGED ? (int)(threadIdx.x / kTile) : 0;
   const int tl = (int)threadIdx.x - half * kTile;  // particle within the tile
   const int i = lb * kTile + tl;
@@ -1442,13 +1507,29 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_forc
   }
 }
 
+template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
+__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force(Dev d, double* __restrict__ f_out,
+                                                     double* __restrict__ sample_out) {
+  (void)sample_out;
+  force_body<MODE, MIXED, BONDS, SAMPLE, STAGED, CAP>(d, xcd_block(d.ntiles), f_out);
+}
+
+// Batched form (the step modes; no per-particle output): one launch over the
+// tiles of every simulation of the batch, XCD-remapped over the whole grid.
+template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
+__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force_b(Batch b) {
+  int sm, lb;
+  locate(b, xcd_map((int)blockIdx.x, (int)gridDim.x), sm, lb);
+  force_body<MODE, MIXED, BONDS, SAMPLE, STAGED, CAP>(*b.dev[sm], lb, nullptr);
+}
+
 // DPD: pack the current velocities and tags of every slot (and zeros for the
 // sentinel slot n) into vt, so that the force kernel gathers one 32-byte
 // record per partner.
-__global__ void __launch_bounds__(kBlock) k_pack_vt(Dev d) {
+__device__ __forceinline__ void pack_vt_body(const Dev& d, int bid) {
   if (d.flags->status) return;
   const Ctrl* c = d.ctrl;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = bid * kBlock + threadIdx.x;
   const int np = d.np;
   double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
   if (i < d.n) {
@@ -1458,19 +1539,27 @@ __global__ void __launch_bounds__(kBlock) k_pack_vt(Dev d) {
   if (i <= d.n) reinterpret_cast<double4*>(d.vt)[i] = v;
 }
 
+__global__ void __launch_bounds__(kBlock) k_pack_vt(Dev d) { pack_vt_body(d, blockIdx.x); }
+
+__global__ void __launch_bounds__(kBlock) k_pack_vt_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  pack_vt_body(*b.dev[sm], bid);
+}
+
 // DPD steps, after k_force<kDpdForce>: u += dt/(2m) F (the step's second
 // half-kick); with SAMPLE the kinetic stress partials of the new full-step
 // velocities go to partials[block][0..5] (the force kernel wrote the virial
 // to [6..11]); unless LAST, the next half-kick and drift follow as in the
 // fused Langevin step.  One thread per slot, blocks of kTile.
 template <bool LAST, bool SAMPLE>
-__global__ void __launch_bounds__(kTile) k_integrate(Dev d) {
+__device__ __forceinline__ void integrate_body(const Dev& d, int bid) {
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
-  const int i = blockIdx.x * kTile + threadIdx.x;
+  const int i = bid * kTile + threadIdx.x;
   const int np = d.np;
   double kin[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double v2 = 0.0;
@@ -1503,13 +1592,23 @@ __global__ void __launch_bounds__(kTile) k_integrate(Dev d) {
     }
     U[i] = ux; U[np + i] = uy; U[2 * np + i] = uz;
   }
-  if (!LAST) vmax_commit<kTile>(d, v2, blockIdx.x);
+  if (!LAST) vmax_commit<kTile>(d, v2, bid);
   if (SAMPLE) {
     double vals[kStressComps];
 #pragma unroll
     for (int k = 0; k < 6; ++k) { vals[k] = kin[k]; vals[6 + k] = 0.0; }
-    block_partials<kTile>(vals, d.partials, blockIdx.x, 6);
+    block_partials<kTile>(vals, d.partials, bid, 6);
   }
+}
+
+template <bool LAST, bool SAMPLE>
+__global__ void __launch_bounds__(kTile) k_integrate(Dev d) { integrate_body<LAST, SAMPLE>(d, blockIdx.x); }
+
+template <bool LAST, bool SAMPLE>
+__global__ void __launch_bounds__(kTile) k_integrate_b(Batch b) {
+  int sm, bid;
+  locate(b, blockIdx.x, sm, bid);
+  integrate_body<LAST, SAMPLE>(*b.dev[sm], bid);
 }
 
 // Stand-alone reduction of the block partials (le_forces, le_stress).
@@ -1519,6 +1618,16 @@ __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
   __syncthreads();
   if (skip) return;
   reduce_partials(d, out6, virial_only != 0);
+}
+
+// Batched form: block k reduces simulation k's partials into out.ptr[k].
+__global__ void k_stress_final_b(Batch b, BatchOut out) {
+  const Dev& d = *b.dev[blockIdx.x];
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = d.flags->status;
+  __syncthreads();
+  if (skip) return;
+  reduce_partials(d, out.ptr[blockIdx.x], false);
 }
 
 // Copy the current control state and speed-bound words into the other copy
@@ -1878,6 +1987,104 @@ hipError_t launch_state_out(const Dev& d, hipStream_t s, double* x, double* u, i
 hipError_t launch_pairs_out(const Dev& d, hipStream_t s, int64_t* pairs, int64_t cap,
                             unsigned long long* counter) {
   hipLaunchKernelGGL(k_pairs_out, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, pairs, cap, counter);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched launchers
+__global__ void k_store_dev(Dev a, Dev b, Dev* dst) {
+  if (threadIdx.x == 0) {
+    dst[0] = a;
+    dst[1] = b;
+  }
+}
+
+hipError_t launch_store_dev(const Dev& a, const Dev& b, Dev* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_dev, dim3(1), dim3(64), 0, s, a, b, dst);
+  return hipGetLastError();
+}
+
+static inline dim3 grid_of(const Batch& b) { return dim3((unsigned)b.start[b.nsims]); }
+
+hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_kick_drift_b, grid_of(par_cur), dim3(kBlock), 0, s, par_cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& par_nxt,
+                            const Batch& tile_nxt, const Dev& cfg, hipStream_t s) {
+  hipLaunchKernelGGL(k_control_bin_b, grid_of(par_cur), dim3(kBlock), 0, s, par_cur);
+  hipLaunchKernelGGL(k_cell_scan_b, grid_of(scan_nxt), dim3(kScanBlock), 0, s, scan_nxt);
+  hipLaunchKernelGGL(k_permute_b, grid_of(par_nxt), dim3(kBlock), 0, s, par_nxt);
+  if (cfg.staged) hipLaunchKernelGGL((k_neighbors_b<kHalo, false>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
+  else if (cfg.small_halo)
+    hipLaunchKernelGGL((k_neighbors_b<kHaloSearch, true>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
+  else hipLaunchKernelGGL((k_neighbors_b<kHalo, true>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
+  return hipGetLastError();
+}
+
+template <int MODE, bool SAMPLE, bool STAGED>
+static void launch_force_bs(const Batch& b, const Dev& cfg, hipStream_t s) {
+  const dim3 g = grid_of(b), blk(STAGED ? kForceTPP * kTile : kTile);
+  const bool bonds = cfg.chain_len > 0;
+  if constexpr (!STAGED && MODE != kDpdForce) {
+    if (cfg.force_cap > 0.0) {
+      if (bonds) hipLaunchKernelGGL((k_force_b<MODE, false, true, SAMPLE, false, true>), g, blk, 0, s, b);
+      else hipLaunchKernelGGL((k_force_b<MODE, false, false, SAMPLE, false, true>), g, blk, 0, s, b);
+      return;
+    }
+  }
+  if (cfg.precision == LE_MIXED) {
+    if (bonds) hipLaunchKernelGGL((k_force_b<MODE, true, true, SAMPLE, STAGED>), g, blk, 0, s, b);
+    else hipLaunchKernelGGL((k_force_b<MODE, true, false, SAMPLE, STAGED>), g, blk, 0, s, b);
+  } else {
+    if (bonds) hipLaunchKernelGGL((k_force_b<MODE, false, true, SAMPLE, STAGED>), g, blk, 0, s, b);
+    else hipLaunchKernelGGL((k_force_b<MODE, false, false, SAMPLE, STAGED>), g, blk, 0, s, b);
+  }
+}
+
+template <int MODE, bool SAMPLE>
+static void launch_force_bt(const Batch& b, const Dev& cfg, hipStream_t s) {
+  if (cfg.staged) launch_force_bs<MODE, SAMPLE, true>(b, cfg, s);
+  else launch_force_bs<MODE, SAMPLE, false>(b, cfg, s);
+}
+
+hipError_t launch_force_b(const Batch& tile_cur, const Batch& par_cur, const Dev& cfg, hipStream_t s,
+                          ForceMode mode, bool sample) {
+  switch (mode) {
+    case kStepLast:
+      if (sample) launch_force_bt<kStepLast, true>(tile_cur, cfg, s);
+      else launch_force_bt<kStepLast, false>(tile_cur, cfg, s);
+      break;
+    case kStepFused:
+      if (sample) launch_force_bt<kStepFused, true>(tile_cur, cfg, s);
+      else launch_force_bt<kStepFused, false>(tile_cur, cfg, s);
+      break;
+    case kDpdForce:
+      if (cfg.staged || !cfg.vt) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_pack_vt_b, grid_of(par_cur), dim3(kBlock), 0, s, par_cur);
+      if (sample) launch_force_bs<kDpdForce, true, false>(tile_cur, cfg, s);
+      else launch_force_bs<kDpdForce, false, false>(tile_cur, cfg, s);
+      break;
+    default:
+      return hipErrorInvalidValue;  // the other modes are not batched
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate_b(const Batch& tile_cur, hipStream_t s, bool last, bool sample) {
+  const dim3 g = grid_of(tile_cur), b(kTile);
+  if (last) {
+    if (sample) hipLaunchKernelGGL((k_integrate_b<true, true>), g, b, 0, s, tile_cur);
+    else hipLaunchKernelGGL((k_integrate_b<true, false>), g, b, 0, s, tile_cur);
+  } else {
+    if (sample) hipLaunchKernelGGL((k_integrate_b<false, true>), g, b, 0, s, tile_cur);
+    else hipLaunchKernelGGL((k_integrate_b<false, false>), g, b, 0, s, tile_cur);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_final_b(const Batch& one_cur, const BatchOut& out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stress_final_b, dim3((unsigned)one_cur.nsims), dim3(kBlock), 0, s, one_cur, out);
   return hipGetLastError();
 }
 

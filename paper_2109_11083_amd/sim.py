@@ -255,3 +255,46 @@ class StepGraph:
         if getattr(self, "handle", None):
             B.le_graph_destroy(self.handle)
             self.handle = None
+
+
+def _rings_for(sims, nsteps: int, sample_every: int, rings):
+    if sample_every <= 0:
+        return None, 0
+    ns = max(nsteps // sample_every, 1)
+    if rings is None:
+        rings = []
+        for s in sims:
+            with torch.cuda.stream(s.stream):
+                rings.append(torch.zeros((ns, 6), dtype=torch.float64, device=s.device))
+    cap = min(r.shape[0] for r in rings)
+    return rings, cap
+
+
+def step_batch(sims, nsteps: int, sample_every: int = 0, rings=None):
+    """Advance several simulations together with le_step_batch (one launch per
+    kernel and kernel configuration for all of them).  They must share one
+    stream.  Returns the per-simulation stress rings (device tensors) when
+    sampling."""
+    rings, cap = _rings_for(sims, nsteps, sample_every, rings)
+    B.le_step_batch([s.handle for s in sims], nsteps, sample_every,
+                    [r.data_ptr() for r in rings] if rings is not None else None, cap)
+    return rings
+
+
+class BatchGraph:
+    """A captured chunk of batched steps (le_batch_graph_create); replay with launch()."""
+
+    def __init__(self, sims, nsteps: int, sample_every: int = 0, rings=None):
+        self.sims = list(sims)
+        self.rings, cap = _rings_for(self.sims, nsteps, sample_every, rings)
+        self.handle = B.le_batch_graph_create([s.handle for s in self.sims], nsteps, sample_every,
+                                              [r.data_ptr() for r in self.rings]
+                                              if self.rings is not None else None, cap)
+
+    def launch(self):
+        B.le_graph_launch(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.le_graph_destroy(self.handle)
+            self.handle = None
