@@ -272,16 +272,26 @@ def viscosity_pair(name, shear_rate, skin, steps=ETA_STEPS, warmup=ETA_WARMUP):
 
 def serving_bench(count=64):
     """Sweep requests (N ~ U{2000..64000}, shear rate log-uniform in [1e-3, 1], 5000 steps,
-    Poisson arrivals at 4/s): continuous batching in mixed precision against FP64 one request at a
-    time (FIFO), on the same trace; plus the same requests all at once (sweep throughput)."""
-    from paper_2109_11083_amd.serve import Server, sweep_trace
-    out = {}
-    runs = [("batched_mixed", "mixed", 16, False), ("fifo_fp64", "fp64", 1, False),
-            ("batched_mixed_burst", "mixed", 16, True), ("fifo_fp64_burst", "fp64", 1, True)]
+    Poisson arrivals at 4/s): continuous batching through le_step_batch in mixed precision
+    against FP64 one request at a time (FIFO) on the same trace; then all requests at once
+    (sweep throughput), batched in both precisions and FIFO.  The cell size and pair
+    layout of the requests come from the batch autotuner on the first 8 requests."""
+    from paper_2109_11083_amd.serve import Server, request_params, sweep_trace
+    from paper_2109_11083_amd.tune import autotune_batch
+    probe = [request_params(r) for r in sweep_trace(count=8, precision="mixed", burst=True)]
+    (skin, tune), table = autotune_batch([(w.x, w.u, p) for w, p in probe])
+    log(f"bench: serving autotune: skin {skin} tune {tune}: "
+        f"{[(a, b, round(c / 1e9, 3)) for a, b, c in table]}")
+    out = dict(autotune=dict(skin=skin, tune=tune,
+                             table=[dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]))
+    runs = [("batched_mixed", "mixed", "batched", 64, False), ("fifo_fp64", "fp64", "streams", 1, False),
+            ("batched_mixed_burst", "mixed", "batched", 64, True),
+            ("batched_fp64_burst", "fp64", "batched", 64, True),
+            ("fifo_fp64_burst", "fp64", "streams", 1, True)]
     etas, ses = {}, {}
-    for name, prec, slots, burst in runs:
-        trace = sweep_trace(count=count, precision=prec, burst=burst)
-        res, summ = Server(max_active=slots).run(trace, realtime=not burst)
+    for name, prec, mode, slots, burst in runs:
+        trace = sweep_trace(count=count, precision=prec, burst=burst, skin=skin, tune=tune)
+        res, summ = Server(max_active=slots, mode=mode).run(trace, realtime=not burst)
         etas[name] = np.array([r.eta for r in res])
         ses[name] = np.array([r.eta_se if r.eta_se is not None else np.nan for r in res])
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
@@ -297,8 +307,12 @@ def serving_bench(count=64):
                                     note="per request, 5000 steps, eta over the second half with its "
                                          "10-block standard error; the two runs of a request are "
                                          "independent trajectories, so the differences are statistical")
+    out["speedup_burst_batched_mixed_vs_fifo_fp64"] = (out["batched_mixed_burst"]["throughput"]
+                                                       / out["fifo_fp64_burst"]["throughput"])
     out["trace"] = dict(requests=count, n="U{2000..64000}", shear_rate="log-U[1e-3, 1]", steps=5000,
-                        arrivals="Poisson 4/s (burst: all at t=0)", skin=0.4)
+                        arrivals="Poisson 4/s (burst: all at t=0)", skin=f"cell-filling skin of {skin}",
+                        tune=tune, batched="le_step_batch chunks of 500 steps (batch graphs)",
+                        fifo="one simulation at a time, le_step chunks (single graphs)")
     return out
 
 

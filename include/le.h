@@ -282,6 +282,12 @@ le_status le_graph_launch(le_graph* g);
 
 le_status le_graph_destroy(le_graph* g);
 
+/* Enqueue a copy of the simulation's latched status (0 or an LE_E_* code) to
+ * the device int32 *status_out, ordered after the work enqueued so far;
+ * does not wait (a caller that tracks its stream with events reads it once
+ * the event has completed). */
+le_status le_status_out(le_sim* s, int32_t* status_out);
+
 /* Wait for all enqueued work of the simulation; returns any latched error. */
 le_status le_sync(le_sim* s);
 

@@ -37,7 +37,7 @@ EXPORTED = [
     "le_get_state", "le_sync", "le_stats", "le_destroy", "le_strerror", "le_offsets", "le_philox",
     "le_timing_enable", "le_timing_read", "le_observables", "le_graph_create", "le_graph_launch",
     "le_graph_destroy", "le_unwrapped", "le_msd", "le_forces_static", "le_step_batch",
-    "le_batch_graph_create",
+    "le_batch_graph_create", "le_status_out",
 ]
 LE_MAX_BINS = 256
 
@@ -117,6 +117,7 @@ def lib() -> C.CDLL:
     L.le_unwrapped.argtypes = [vp, vp]
     L.le_msd.argtypes = [vp, vp, vp]
     L.le_forces_static.argtypes = [P, vp, vp, vp, vp, i64, vp]
+    L.le_status_out.argtypes = [vp, vp]
     L.le_step_batch.argtypes = [C.POINTER(vp), i32, i64, i32, C.POINTER(vp), i64]
     L.le_batch_graph_create.argtypes = [C.POINTER(vp), i32, i64, i32, C.POINTER(vp), i64, sim_pp]
     for name in EXPORTED:
@@ -201,6 +202,10 @@ def le_get_state(sim: int, x: int | None, u: int | None, f: int | None) -> int:
     step = C.c_int64(0)
     check(lib().le_get_state(sim, x, u, f, C.byref(step)), "le_get_state")
     return step.value
+
+
+def le_status_out(sim: int, status_out: int) -> None:
+    check(lib().le_status_out(sim, status_out), "le_status_out")
 
 
 def le_sync(sim: int) -> int:

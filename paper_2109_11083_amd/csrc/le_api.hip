@@ -811,6 +811,11 @@ le_status le_graph_destroy(le_graph* g) {
   return LE_OK;
 }
 
+le_status le_status_out(le_sim* s, int32_t* status_out) {
+  if (!s || !status_out) return LE_E_ARG;
+  return hip_check(launch_status_out(s->d, s->stream, status_out));
+}
+
 le_status le_sync(le_sim* s) {
   if (!s) return LE_E_ARG;
   return read_status(s);

@@ -45,6 +45,16 @@ __device__ __forceinline__ void locate(const Batch& b, int g, int& sim, int& bid
   bid = g - b.start[lo];
 }
 
+// The descriptor of a batched launch's simulation.  It never changes while
+// kernels run (written once at le_init), so it is read as constant memory:
+// through an address-space-4 pointer the loads become scalar loads into SGPRs,
+// as for the by-value descriptor of a single-simulation launch.
+static_assert(sizeof(Dev) % 8 == 0, "the descriptor is a whole number of 8-byte words");
+typedef const __attribute__((address_space(4))) Dev ConstDev;
+__device__ __forceinline__ const Dev& stage_dev(const Dev* src) {
+  return *(const Dev*)(ConstDev*)src;
+}
+
 __device__ __forceinline__ void latch(Flags* f, int32_t st) { atomicCAS(&f->status, 0, st); }
 
 // Canonical periodic wrap into [0, L); returns the net number of box lengths
@@ -301,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_control_bin(Dev d, Ctrl* __restrict_
 __global__ void __launch_bounds__(kBlock) k_control_bin_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  const Dev& d = *b.dev[sm];
+  const Dev& d = stage_dev(b.dev[sm]);
   control_bin_body(d, d.ctrl_other, d.vmax_other, 0, 1, bid);
 }
 
@@ -405,7 +415,7 @@ __global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) { cell_scan_bod
 __global__ void __launch_bounds__(kScanBlock) k_cell_scan_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  cell_scan_body(*b.dev[sm], bid);
+  cell_scan_body(stage_dev(b.dev[sm]), bid);
 }
 
 // (3) Final slot = cell start + number of cell-mates with a smaller tag, so
@@ -441,7 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_permute(Dev d) { permute_body(d, blo
 __global__ void __launch_bounds__(kBlock) k_permute_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  permute_body(*b.dev[sm], bid);
+  permute_body(stage_dev(b.dev[sm]), bid);
 }
 
 // Neighbour lists of radius r_list through the Lees-Edwards cell stencil.
@@ -920,7 +930,7 @@ template <int HALO, bool GL>
 __global__ void __launch_bounds__(2 * kTile) k_neighbors_b(Batch b) {
   int sm, tile;
   locate(b, xcd_map((int)blockIdx.x, (int)gridDim.x), sm, tile);
-  neighbors_body<HALO, GL>(*b.dev[sm], tile);
+  neighbors_body<HALO, GL>(stage_dev(b.dev[sm]), tile);
 }
 
 // ---------------------------------------------------------- integrator
@@ -1009,7 +1019,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(Dev d) { kick_drift_body(
 __global__ void __launch_bounds__(kBlock) k_kick_drift_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  kick_drift_body(*b.dev[sm], bid);
+  kick_drift_body(stage_dev(b.dev[sm]), bid);
 }
 
 // ---------------------------------------------------------- force kernel
@@ -1520,7 +1530,7 @@ template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP =
 __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force_b(Batch b) {
   int sm, lb;
   locate(b, xcd_map((int)blockIdx.x, (int)gridDim.x), sm, lb);
-  force_body<MODE, MIXED, BONDS, SAMPLE, STAGED, CAP>(*b.dev[sm], lb, nullptr);
+  force_body<MODE, MIXED, BONDS, SAMPLE, STAGED, CAP>(stage_dev(b.dev[sm]), lb, nullptr);
 }
 
 // DPD: pack the current velocities and tags of every slot (and zeros for the
@@ -1544,7 +1554,7 @@ __global__ void __launch_bounds__(kBlock) k_pack_vt(Dev d) { pack_vt_body(d, blo
 __global__ void __launch_bounds__(kBlock) k_pack_vt_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  pack_vt_body(*b.dev[sm], bid);
+  pack_vt_body(stage_dev(b.dev[sm]), bid);
 }
 
 // DPD steps, after k_force<kDpdForce>: u += dt/(2m) F (the step's second
@@ -1608,7 +1618,7 @@ template <bool LAST, bool SAMPLE>
 __global__ void __launch_bounds__(kTile) k_integrate_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  integrate_body<LAST, SAMPLE>(*b.dev[sm], bid);
+  integrate_body<LAST, SAMPLE>(stage_dev(b.dev[sm]), bid);
 }
 
 // Stand-alone reduction of the block partials (le_forces, le_stress).
@@ -1622,7 +1632,7 @@ __global__ void k_stress_final(Dev d, double* out6, int virial_only) {
 
 // Batched form: block k reduces simulation k's partials into out.ptr[k].
 __global__ void k_stress_final_b(Batch b, BatchOut out) {
-  const Dev& d = *b.dev[blockIdx.x];
+  const Dev& d = stage_dev(b.dev[blockIdx.x]);
   __shared__ int skip;
   if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();

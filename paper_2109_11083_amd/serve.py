@@ -2,16 +2,26 @@
 
 Requests (independent Lees-Edwards simulations of different size and shear
 rate) arrive over time.  The server admits a request when its device
-footprint (workspace + sample ring) fits the HBM budget and a slot is free,
-gives it its own HIP stream, and advances every admitted simulation in
-chunks of steps, so the work of several requests overlaps on the device.  A
-request finishes when its steps are done; its result is the sampled shear
-stress series and the viscosity estimate.  Time-to-result is completion
-minus arrival.
+footprint (workspace + sample ring) fits the HBM budget and a slot is free;
+a request finishes when its steps are done, and its result is the sampled
+shear-stress series and the viscosity estimate (Eq. viscosity).
+Time-to-result is completion minus arrival.
 
-Each simulation is deterministic and independent of the others (own
-workspace, own stream, own Philox key), so its result is the same alone and
-in the mix.
+Two ways to advance the admitted simulations:
+
+* ``mode="batched"`` (continuous batching): every admitted simulation lives
+  on the server's one stream, and each chunk of steps advances all of them
+  together with le_step_batch (one launch per kernel for the whole batch,
+  or one replay of a captured batch graph while the batch is unchanged).
+  Requests that arrive while others run join at the next chunk boundary;
+  finished ones leave at theirs.
+* ``mode="streams"``: each simulation gets its own stream and its own
+  le_step (or single-simulation graph) per chunk; with ``max_active=1`` this
+  is the plain one-simulation-at-a-time (FIFO) baseline.
+
+Every simulation is deterministic and independent of the others (own
+workspace, own Philox key, its own descriptor in a batch), so its result is
+bitwise the same alone and in the mix, in either mode.
 """
 from __future__ import annotations
 
@@ -22,8 +32,9 @@ import time
 import numpy as np
 import torch
 
+from . import binding as B
 from . import inputs
-from .sim import Params, Sim
+from .sim import BatchGraph, Params, Sim, step_batch
 
 
 @dataclasses.dataclass
@@ -37,6 +48,7 @@ class Request:
     precision: str = "fp64"
     skin: float = 0.4
     sample_every: int = 10
+    tune: int = 0
 
 
 @dataclasses.dataclass
@@ -60,7 +72,7 @@ class Result:
 
 
 def sweep_trace(count=64, rate=4.0, n_lo=2000, n_hi=64000, sr_lo=1e-3, sr_hi=1.0, steps=5000,
-                seed=41, precision="fp64", burst=False):
+                seed=41, precision="fp64", burst=False, skin=0.4, tune=0):
     """Requests with N ~ U{n_lo..n_hi}, shear rate log-uniform, Poisson arrivals
     (mean gap 1/rate; all at t = 0 when burst)."""
     rng = np.random.default_rng(seed)
@@ -71,20 +83,39 @@ def sweep_trace(count=64, rate=4.0, n_lo=2000, n_hi=64000, sr_lo=1e-3, sr_hi=1.0
             t += float(rng.exponential(1.0 / rate))
         n = int(rng.integers(n_lo, n_hi + 1))
         sr = float(math.exp(rng.uniform(math.log(sr_lo), math.log(sr_hi))))
-        out.append(Request(k, 0.0 if burst else t, n, sr, steps, 100 * seed + k, precision))
+        out.append(Request(k, 0.0 if burst else t, n, sr, steps, 100 * seed + k, precision, skin=skin,
+                           tune=tune))
     return out
 
 
 def request_params(r: Request) -> tuple:
+    """LJ fluid of the request (density 0.8442, r_c 2.5, kT 1, Langevin gamma 1, dt 0.005).
+    The skin is the request's, widened to fill the cells of its box (same cells, rarer
+    rebuilds)."""
+    from .tune import filling_skin
     w = inputs.lj_workload(n=r.n, shear_rate=r.shear_rate, seed=r.seed)
     p = Params(n=w.x.shape[1], box=w.box, shear_rate=r.shear_rate, seed=r.seed, skin=r.skin,
-               precision=r.precision, rc=2.5, dt=0.005, kT=1.0, gamma=1.0)
+               precision=r.precision, rc=2.5, dt=0.005, kT=1.0, gamma=1.0, tune=r.tune)
+    f = filling_skin(p, r.skin)
+    if f is not None:
+        p = dataclasses.replace(p, skin=f)
     return w, p
 
 
 def footprint(p: Params, r: Request) -> int:
     from .sim import workspace_bytes
     return workspace_bytes(p) + (r.steps // r.sample_every + 1) * 6 * 8 + 6 * p.n * 8
+
+
+def eta_of_series(sig: np.ndarray, shear_rate: float):
+    """Viscosity over the second half of the samples and its 10-block standard error."""
+    half = sig[len(sig) // 2:]
+    eta = float(half[:, 3].mean() / shear_rate)
+    eta_se = None
+    if len(half) >= 20:
+        blocks = half[: len(half) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / shear_rate
+        eta_se = float(blocks.std(ddof=1) / np.sqrt(10))
+    return eta, eta_se
 
 
 class _Active:
@@ -95,25 +126,169 @@ class _Active:
         self.admitted = admitted
         self.nbytes = nbytes
         self.issued = 0         # steps enqueued
-        self.events = []        # (steps covered, event) per enqueued chunk
-        self.graph = None       # captured chunk (HIP graph) and its sample rows
+        self.events = []        # (steps covered, event) per enqueued chunk (streams mode)
+        self.graph = None       # captured chunk (HIP graph) and its sample rows (streams mode)
         self.graph_ring = None
+        self.status = None      # device int32: latched status after the last chunk (batched mode)
+
+
+@dataclasses.dataclass
+class _Chunk:
+    event: torch.cuda.Event
+    finishing: list          # members whose last step is in this chunk
+    keep: object = None      # graph used by the chunk (destroyed once it has run)
 
 
 class Server:
     """Continuous-batching server.  hbm_budget: bytes the admitted requests may
-    hold; max_active: concurrent simulations (streams); chunk: steps per
-    enqueue; keep_state: copy the final state of each request (tests)."""
+    hold; max_active: concurrent simulations; chunk: steps per enqueue; ahead:
+    chunks in flight; keep_state: copy the final state of each request (tests);
+    graphs: replay captured chunks; mode: "batched" or "streams" (see module)."""
 
-    def __init__(self, hbm_budget=16 << 30, max_active=16, chunk=500, ahead=2, keep_state=False,
-                 graphs=True):
+    def __init__(self, hbm_budget=16 << 30, max_active=64, chunk=500, ahead=2, keep_state=False,
+                 graphs=True, mode="batched"):
+        assert mode in ("batched", "streams")
         self.hbm_budget = hbm_budget
         self.max_active = max_active
         self.chunk = chunk
         self.ahead = ahead
         self.keep_state = keep_state
         self.graphs = graphs
+        self.mode = mode
 
+    # ------------------------------------------------------------ shared
+    def _finish(self, a: _Active, now: float) -> Result:
+        r = a.req
+        if a.status is not None and not self.keep_state:
+            # batched: the chunk holding the last step has completed, and the
+            # status copy enqueued after it is final; no wait on the shared stream
+            st = int(a.status.cpu()[0])
+            if st != 0:
+                raise B.LeError(st, f"request {r.rid}")
+        else:
+            a.sim.stream.synchronize()
+            a.sim.sync()
+        sig = a.ring.cpu().numpy()
+        eta, eta_se = eta_of_series(sig, r.shear_rate)
+        xs = us = None
+        if self.keep_state:
+            xs, us, _, _ = a.sim.state()
+        if a.graph is not None:
+            a.graph.close()
+        a.sim.close()
+        return Result(r.rid, r.arrival, a.admitted, now, r.n, r.steps, r.shear_rate, eta, sig, xs, us,
+                      eta_se=eta_se)
+
+    def _admit(self, pending, active, used, t0, realtime, stream):
+        """Admit arrived requests in arrival order while slots and HBM allow."""
+        now = time.perf_counter() - t0
+        while pending and (pending[0].arrival <= now or not realtime) and len(active) < self.max_active:
+            req = pending[0]
+            w, p = request_params(req)
+            nb = footprint(p, req)
+            if active and used + nb > self.hbm_budget:
+                break
+            pending.pop(0)
+            st = stream if stream is not None else torch.cuda.Stream()
+            sim = Sim(p, w.x, w.u, step0=0, stream=st, sync=stream is None)
+            with torch.cuda.stream(st):
+                ring = torch.zeros((req.steps // req.sample_every, 6), dtype=torch.float64,
+                                   device="cuda")
+            active.append(_Active(req, sim, ring, time.perf_counter() - t0, nb))
+            used += nb
+        return used
+
+    def run(self, trace, realtime=True):
+        """Serve the trace; returns the results in request order and a summary."""
+        if self.mode == "batched":
+            results = self._run_batched(trace, realtime)
+        else:
+            results = self._run_streams(trace, realtime)
+        results.sort(key=lambda q: q.rid)
+        return results, summarize(results)
+
+    # ------------------------------------------------------------ batched
+    def _enqueue_batch(self, members, k, se, stream, state):
+        """One chunk of k steps for every member: a replay of the cached batch graph
+        when the batch is the one it was captured for, else le_step_batch (and a
+        capture for the next chunk of the same batch)."""
+        key = (tuple(id(a) for a in members), k)
+        rows = [a.issued // se for a in members]
+        keep = None
+        if self.graphs and k % 2 == 0 and k % se == 0:
+            if state.get("key") != key:
+                old = state.pop("graph", None)
+                if old is not None:
+                    state.setdefault("retired", []).append(old)
+                with torch.cuda.stream(stream):
+                    grings = [torch.zeros((k // se, 6), dtype=torch.float64, device="cuda")
+                              for _ in members]
+                state["graph"] = BatchGraph([a.sim for a in members], k, sample_every=se, rings=grings)
+                state["key"] = key
+            g = state["graph"]
+            g.launch()
+            with torch.cuda.stream(stream):
+                for a, r0, gr in zip(members, rows, g.rings):
+                    a.ring[r0:r0 + gr.shape[0]].copy_(gr)
+            keep = g
+        else:
+            rings = [a.ring[r0:] for a, r0 in zip(members, rows)]
+            cap = min(r.shape[0] for r in rings)
+            B.le_step_batch([a.sim.handle for a in members], k, se, [r.data_ptr() for r in rings], cap)
+        return keep
+
+    def _run_batched(self, trace, realtime):
+        pending = sorted(trace, key=lambda q: (q.arrival, q.rid))
+        se = pending[0].sample_every if pending else 10
+        assert all(q.sample_every == se for q in pending), "one sampling interval per server"
+        stream = torch.cuda.Stream()
+        active: list[_Active] = []
+        inflight: list[_Chunk] = []
+        results = []
+        used = 0
+        state = {}
+        t0 = time.perf_counter()
+        while pending or active:
+            progressed = False
+            while inflight and inflight[0].event.query():
+                ch = inflight.pop(0)
+                now = time.perf_counter() - t0
+                for a in ch.finishing:
+                    results.append(self._finish(a, now))
+                    used -= a.nbytes
+                    active.remove(a)
+                progressed = True
+            if not inflight:
+                for g in state.pop("retired", []):
+                    g.close()
+            used = self._admit(pending, active, used, t0, realtime, stream)
+            while len(inflight) < self.ahead:
+                members = [a for a in active if a.issued < a.req.steps]
+                if not members:
+                    break
+                k = min(self.chunk, min(a.req.steps - a.issued for a in members))
+                keep = self._enqueue_batch(members, k, se, stream, state)
+                for a in members:
+                    a.issued += k
+                    if a.issued >= a.req.steps:
+                        with torch.cuda.stream(stream):
+                            a.status = torch.full((1,), -99, dtype=torch.int32, device="cuda")
+                        B.le_status_out(a.sim.handle, a.status.data_ptr())
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                inflight.append(_Chunk(ev, [a for a in members if a.issued >= a.req.steps], keep))
+                progressed = True
+            if not progressed:
+                if inflight:
+                    time.sleep(50e-6)
+                elif pending and realtime:
+                    time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
+        stream.synchronize()
+        for g in state.pop("retired", []) + ([state["graph"]] if "graph" in state else []):
+            g.close()
+        return results
+
+    # ------------------------------------------------------------ streams
     def _enqueue(self, a: _Active):
         r = a.req
         k = min(self.chunk, r.steps - a.issued)
@@ -139,51 +314,16 @@ class Server:
         a.issued += k
         a.events.append((a.issued, ev))
 
-    def _finish(self, a: _Active, now: float) -> Result:
-        r = a.req
-        a.sim.stream.synchronize()
-        a.sim.sync()
-        sig = a.ring.cpu().numpy()
-        half = sig[len(sig) // 2:]
-        eta = float(half[:, 3].mean() / r.shear_rate)
-        eta_se = None
-        if len(half) >= 20:
-            blocks = half[: len(half) // 10 * 10, 3].reshape(10, -1).mean(axis=1) / r.shear_rate
-            eta_se = float(blocks.std(ddof=1) / np.sqrt(10))
-        xs = us = None
-        if self.keep_state:
-            xs, us, _, _ = a.sim.state()
-        if a.graph is not None:
-            a.graph.close()
-        a.sim.close()
-        return Result(r.rid, r.arrival, a.admitted, now, r.n, r.steps, r.shear_rate, eta, sig, xs, us,
-                      eta_se=eta_se)
-
-    def run(self, trace, realtime=True):
-        """Serve the trace; returns the results in request order and a summary."""
+    def _run_streams(self, trace, realtime):
         pending = sorted(trace, key=lambda q: (q.arrival, q.rid))
         active: list[_Active] = []
         results = []
         used = 0
         t0 = time.perf_counter()
         while pending or active:
-            now = time.perf_counter() - t0
-            # admit arrived requests in arrival order while slots and HBM allow
-            while pending and (pending[0].arrival <= now or not realtime) and len(active) < self.max_active:
-                req = pending[0]
-                w, p = request_params(req)
-                nb = footprint(p, req)
-                if active and used + nb > self.hbm_budget:
-                    break
-                pending.pop(0)
-                stream = torch.cuda.Stream()
-                sim = Sim(p, w.x, w.u, step0=0, stream=stream)
-                with torch.cuda.stream(stream):
-                    ring = torch.zeros((req.steps // req.sample_every, 6), dtype=torch.float64,
-                                       device="cuda")
-                a = _Active(req, sim, ring, time.perf_counter() - t0, nb)
-                used += nb
-                active.append(a)
+            n_before = len(active)
+            used = self._admit(pending, active, used, t0, realtime, None)
+            for a in active[n_before:]:
                 for _ in range(self.ahead):
                     self._enqueue(a)
             # progress: retire finished chunks, keep `ahead` chunks in flight
@@ -204,8 +344,7 @@ class Server:
                     time.sleep(50e-6)
                 elif pending and realtime:
                     time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
-        results.sort(key=lambda q: q.rid)
-        return results, summarize(results)
+        return results
 
 
 def summarize(results) -> dict:

@@ -94,7 +94,8 @@ class Sim:
     """One Lees-Edwards simulation living in a torch-allocated workspace."""
 
     def __init__(self, params: Params, x0, u0, step0: int = 0, f0=None, device="cuda",
-                 stream: torch.cuda.Stream | None = None, workspace: torch.Tensor | None = None):
+                 stream: torch.cuda.Stream | None = None, workspace: torch.Tensor | None = None,
+                 sync: bool = True):
         self.params = params
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -115,10 +116,12 @@ class Sim:
                                     f0.data_ptr() if f0 is not None else None,
                                     workspace.data_ptr(), workspace.numel(), self.stream.cuda_stream,
                                     int(step0))
-        # inputs must outlive the asynchronous copy in le_init
+        # inputs must outlive the asynchronous copy in le_init: wait for it, or
+        # (sync=False, e.g. a server whose stream is busy) keep them until close
         self._keep = (x0, u0, f0)
-        self.stream.synchronize()
-        self._keep = None
+        if sync:
+            self.stream.synchronize()
+            self._keep = None
 
     # ---------------------------------------------------------------- calls
     def build_cells(self, want_pairs: bool = True):

@@ -63,3 +63,48 @@ def autotune(p: Params, x0, u0, skins=(0.2, 0.3, 0.4, 0.5, 0.6, 0.8), tunes=(0,)
     if best is None:
         raise RuntimeError("no candidate layout is valid for this system")
     return dataclasses.replace(p, skin=best[0], tune=best[1]), table
+
+
+def autotune_batch(members, skins=(0.2, 0.3, 0.4, 0.5, 0.6), tunes=(1, 2), steps=300, warmup=60):
+    """Cell size and tile schedule for a batch.  members: list of (x0, u0, Params).
+    Each candidate (skin, tune) gives every member the cell-filling skin of `skin`
+    in its own box (its cell size) and the pair layout `tune` (1: partners staged
+    per tile in LDS, 2: partners from global memory); the batch then runs one burst
+    through le_step_batch on a fresh stream.  Returns ((skin, tune), table of
+    (skin, tune, particle-steps/s))."""
+    from .sim import step_batch
+    table = []
+    best = None
+    work = sum(p.n for _, _, p in members) * steps
+    for tune in tunes:
+        for skin in skins:
+            stream = torch.cuda.Stream()
+            sims = []
+            try:
+                for x0, u0, p in members:
+                    f = filling_skin(p, skin)
+                    q = dataclasses.replace(p, skin=float(f if f is not None else skin), tune=int(tune))
+                    sims.append(Sim(q, x0, u0, stream=stream))
+            except Exception:  # a geometry this skin does not allow
+                for s in sims:
+                    s.close()
+                continue
+            try:
+                step_batch(sims, warmup)
+                stream.synchronize()
+                t0 = time.perf_counter()
+                step_batch(sims, steps)
+                stream.synchronize()
+                t1 = time.perf_counter()
+                for s in sims:
+                    s.sync()
+            finally:
+                for s in sims:
+                    s.close()
+            rate = work / (t1 - t0)
+            table.append((float(skin), int(tune), rate))
+            if best is None or rate > best[2]:
+                best = (float(skin), int(tune), rate)
+    if best is None:
+        raise RuntimeError("no candidate is valid for every member")
+    return (best[0], best[1]), table
