@@ -100,21 +100,24 @@ def kg_state(shear_rate, seed=31):
 
 
 def workload(name, shear_rate, precision, skin=0.3, n=256000, thermostat="langevin"):
-    """(x, u, Params) of a named workload."""
+    """(x, u, Params) of a named workload; skin may be a (skin, pair layout) pair."""
     import dataclasses
+    skin, tune = skin if isinstance(skin, tuple) else (skin, 0)
     if name == "kg":
         x, u, _ = kg_state(shear_rate)
-        return x, u, kg_params(shear_rate, precision, skin=skin)
+        return x, u, dataclasses.replace(kg_params(shear_rate, precision, skin=skin), tune=tune)
     x, u, p = lj_params(n, shear_rate, precision, skin=skin, thermostat=thermostat)
-    return x, u, dataclasses.replace(p)
+    return x, u, dataclasses.replace(p, tune=tune)
 
 
 def pick_skin(name, shear_rate, precision, n=256000, thermostat="langevin"):
-    """Autotuned skin (short bursts of the cell-filling skins; paper_2109_11083_amd.tune)."""
+    """Autotuned skin and pair layout (short bursts of the cell-filling skins with the
+    LDS-halo and the global-memory layouts; paper_2109_11083_amd.tune)."""
     from paper_2109_11083_amd.tune import autotune
     x, u, p = workload(name, shear_rate, precision, n=n, thermostat=thermostat)
-    best, table = autotune(p, x, u)
-    return best.skin, [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
+    tunes = (2,) if thermostat == "dpd" else (1, 2)
+    best, table = autotune(p, x, u, tunes=tunes)
+    return (best.skin, best.tune), [dict(skin=a, tune=b, value=round(c, 1)) for a, b, c in table]
 
 
 # ------------------------------------------------------------------ one timed run
@@ -316,6 +319,90 @@ def serving_bench(count=64):
     return out
 
 
+def c5_sweep(scale=0.1, steps=30000, warmup=1000, seed=51, dt=0.005):
+    """The mixed-precision batched sweep: 16 Kremer-Grest melts (chains ~ U{500..2000} x scale,
+    lengths ~ U{100..400}, density 0.85, WCA + FENE, random walks warmed up together with
+    capped forces), shear rate 10^(-4 + 3k/15) for melt k, advanced as ONE batch
+    (le_step_batch) in FP64 and again in mixed precision from the same warmed states.
+    Reports both batch throughputs and, per melt, eta +- block SE in each precision with
+    their difference in combined standard errors (the FP64 path is the reference: the
+    oracle checks it on short windows, and no CPU run reaches these lengths).  dt = 0.005: at
+    0.01 the gamma_dot = 0.1 melt of the longest chains stretches a FENE bond past R0 after
+    ~1.1e4 steps, in either precision; at 0.005 every melt runs 3e4 steps.  A member that
+    still latches an error is reported and left out of the comparison."""
+    import dataclasses
+    import torch
+    from paper_2109_11083_amd import inputs
+    from paper_2109_11083_amd.sim import Params, Sim, step_batch
+    from paper_2109_11083_amd.tune import autotune_batch, filling_skin
+    from paper_2109_11083_amd.warmup import warm_up_many
+    rng = np.random.default_rng(seed)
+    melts = []
+    for k in range(16):
+        nc = max(2, int(round(int(rng.integers(500, 2001)) * scale)))
+        cl = int(rng.integers(100, 401))
+        sr = 10.0 ** (-4.0 + 3.0 * k / 15.0)
+        w = inputs.kg_workload(nc, cl, shear_rate=0.0, seed=seed * 100 + k, layout="walk")
+        p = Params(n=w.x.shape[1], box=w.box, shear_rate=sr, seed=seed * 100 + k, rc=2.0 ** (1.0 / 6.0),
+                   pair="wca", n_chains=nc, chain_len=cl, dt=dt, kT=1.0, gamma=0.5)
+        melts.append((p, w.x, w.u))
+    t0 = time.perf_counter()
+    warmed = warm_up_many(melts)
+    log(f"bench: c5 warm-up of 16 melts ({sum(p.n for p, _, _ in melts)} beads) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    states = []
+    for (p, _, _), (x, c, _) in zip(melts, warmed):
+        states.append((x, inputs.streaming_initial_velocity(x, c, p.shear_rate, p.box[1]), p))
+    (skin, tune), table = autotune_batch(states, skins=(0.4, 0.5, 0.6, 0.8), tunes=(2,), steps=300)
+    log(f"bench: c5 batch autotune skin {skin}: {[(a, round(v / 1e9, 3)) for a, _, v in table]}")
+    out = dict(melts=[], skin=skin, tune=tune, steps=steps, warmup=warmup)
+    etas = {}
+    for prec in ("fp64", "mixed"):
+        stream = torch.cuda.Stream()
+        sims = []
+        for x, u, p in states:
+            f = filling_skin(p, skin)
+            sims.append(Sim(dataclasses.replace(p, precision=prec, skin=f if f else skin, tune=tune), x, u,
+                            stream=stream))
+        step_batch(sims, warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        rings = step_batch(sims, steps, sample_every=10)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        failed = {}
+        for k, s in enumerate(sims):
+            try:
+                s.sync()
+            except Exception as exc:  # noqa: BLE001 - a latched device error of one melt
+                failed[k] = str(exc)
+        out[f"failed_{prec}"] = failed
+        ntot = sum(s.params.n for s in sims)
+        out[f"throughput_{prec}"] = ntot * steps / (t1 - t0)
+        etas[prec] = [eta_of(r.cpu().numpy(), s.params.shear_rate) if k not in failed else (None, None)
+                      for k, (r, s) in enumerate(zip(rings, sims))]
+        for s in sims:
+            s.close()
+        log(f"bench: c5 batch {prec}: {ntot} beads, {out[f'throughput_{prec}']:.4e} p-steps/s")
+    zs = []
+    for k, (x, u, p) in enumerate(states):
+        (e64, s64), (e32, s32) = etas["fp64"][k], etas["mixed"][k]
+        z = abs(e32 - e64) / math.hypot(s64, s32) if (s64 and s32 and e64 is not None and e32 is not None) else None
+        if z is not None:
+            zs.append(z)
+        out["melts"].append(dict(chains=p.n_chains, length=p.chain_len, n=p.n, shear_rate=p.shear_rate,
+                                 strain=p.shear_rate * p.dt * steps, eta_fp64=e64, se_fp64=s64,
+                                 eta_mixed=e32, se_mixed=s32, diff_in_se=z))
+    zs = np.array(zs)
+    out["mixed_speedup"] = out["throughput_mixed"] / out["throughput_fp64"]
+    out["eta_agreement"] = dict(median_diff_in_se=float(np.median(zs)), frac_within_2se=float((zs <= 2).mean()),
+                                frac_within_3se=float((zs <= 3).mean()),
+                                note="eta over the last 20% of each run, 10-block SE; the two runs "
+                                     "of a melt are independent trajectories (statistical differences)")
+    out["scale"] = scale
+    return out
+
+
 def host_info():
     info = dict(nproc=os.cpu_count())
     try:
@@ -388,6 +475,12 @@ def main():
                     help="no HIP events in the timed region (then no per-kernel roofline)")
     ap.add_argument("--skin", default="auto",
                     help="neighbour-list skin, or 'auto' (autotuned per workload, short bursts)")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="pair layout with an explicit --skin: 0 from density, 1 LDS halo, 2 global")
+    ap.add_argument("--c5-scale", type=float, default=0.1,
+                    help="chain counts of the 16-melt mixed-precision sweep as a fraction of "
+                         "U{500..2000} (1.0: the full sweep, up to 800k beads per melt)")
+    ap.add_argument("--c5-steps", type=int, default=30000)
     ap.add_argument("--workload", default="kg", choices=["kg", "lj"],
                     help="kg: 2000 x 200 Kremer-Grest melt (the headline); lj: 256,000-particle LJ fluid")
     ap.add_argument("--thermostat", default="langevin", choices=["langevin", "dpd", "langevin_abs"],
@@ -417,16 +510,16 @@ def main():
     tune_table = None
     if args.skin == "auto":
         skin, tune_table = pick_skin(args.workload, sr, args.precision, n=args.n, thermostat=th)
-        log(f"bench: autotuned skin {skin}: {tune_table}")
+        log(f"bench: autotuned skin, layout {skin}: {tune_table}")
     else:
-        skin = float(args.skin)
+        skin = (float(args.skin), args.tune)
     x, u, p = workload(args.workload, sr, args.precision, skin=skin, n=args.n, thermostat=th)
     log(f"bench: {args.workload} n={p.n} shear_rate={sr} {args.precision} steps={args.steps} "
         f"warmup={args.warmup} skin={skin}")
     r = run_gpu(x, u, p, args.steps, args.warmup, timing=0 if args.no_timing else TIMING_FORCE)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
-    roofline = roofline_of(r, args.workload, args.precision, skin, dpd=dpd)
+    roofline = roofline_of(r, args.workload, args.precision, skin[0], dpd=dpd)
 
     extra = {}
     # per-phase device time of the same workload (all phases event-timed; a separate, shorter run)
@@ -450,9 +543,9 @@ def main():
             ljskin, ljtable = pick_skin("lj", 0.1, "fp64")
             x2, u2, p2 = workload("lj", 0.1, "fp64", skin=ljskin)
             e = run_gpu(x2, u2, p2, 2000, 100)
-            extra["lj_256k"] = dict(value=e["value"], ms_per_step=e["ms_per_step"], skin=ljskin,
-                                    rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
-                                    roofline=roofline_of(e, "lj", "fp64", ljskin), skin_autotune=ljtable)
+            extra["lj_256k"] = dict(value=e["value"], ms_per_step=e["ms_per_step"], skin=ljskin[0],
+                                    tune=ljskin[1], rebuilds_per_1000=1000 * e["rebuilds"] / 2000,
+                                    roofline=roofline_of(e, "lj", "fp64", ljskin[0]), skin_autotune=ljtable)
             log(f"bench: lj 256k: {e['value']:.4e} p-steps/s")
         else:
             ljskin = skin
@@ -465,6 +558,8 @@ def main():
         # viscosity in FP64 and mixed precision from fixed-length runs (Eq. viscosity)
         viscosity = dict(lj_256k_shear_rate_0_1=guarded("lj viscosity", lambda: viscosity_pair("lj", 0.1, ljskin)))
         kskin = skin if kg else pick_skin("kg", 0.01, "fp64")[0]
+        extra["c5_mixed_batched_kg_sweep"] = guarded(
+            "c5 sweep", lambda: c5_sweep(scale=args.c5_scale, steps=args.c5_steps))
         for sr3 in (0.01, 0.1):
             viscosity[f"kg_400k_shear_rate_{sr3}"] = guarded(
                 "kg viscosity", lambda: viscosity_pair("kg", sr3, kskin, steps=20000, warmup=1000))
@@ -517,7 +612,8 @@ def main():
             "shear_rate": sr,
             "precision": args.precision,
             "stress_sample_every": 10,
-            "skin": skin,
+            "skin": skin[0],
+            "pair_layout": {0: "from density", 1: "LDS halo", 2: "global"}[skin[1]],
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
