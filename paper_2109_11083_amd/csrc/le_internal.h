@@ -16,6 +16,7 @@ constexpr int kHaloSearch = 1536;  // the same for the list search alone (system
 static_assert(kHaloSearch <= kHalo, "the halo tables are sized for kHalo");
 static_assert(kHalo % (4 * kTile) == 0, "halo staging loops assume whole rounds of the tile");
 constexpr int kForceTPP = 4;       // threads per particle of the halo-layout force kernel
+constexpr int kGlobalTPP = 1;      // threads per particle of the global-layout force kernel (2: one per sub-list)
 static_assert(kHalo % (kForceTPP * kTile) == 0, "halo staging rounds of the force kernel");
 constexpr int kMaxRows = 3;        // cell rows a tile may span and still be staged
 constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile

@@ -1171,7 +1171,9 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
   constexpr bool DPD = MODE == kDpdForce;
   static_assert(!DPD || !STAGED, "DPD partners come from global memory");
   constexpr int kH = STAGED ? kHalo + 1 : 1;  // no halo: every partner from global memory
-  constexpr int kTh = STAGED ? kForceTPP * kTile : kTile;  // threads per block
+  constexpr int TPP = STAGED ? kForceTPP : kGlobalTPP;  // threads per particle
+  constexpr int kTh = TPP * kTile;                      // threads per block
+  static_assert(STAGED || TPP <= 2, "global layout: at most one thread per sub-list");
   static_assert(!STAGED || 3 * kH >= kTile * 9 * (kForceTPP - 1), "the halo holds the partial-sum exchange");
   __shared__ double hbuf[3 * kH];
   double* const hx = hbuf;
@@ -1182,7 +1184,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
   if (threadIdx.x == 0) skip = d.flags->status;
   __syncthreads();
   if (skip) return;
-  const int half = STAGED ? (int)(threadIdx.x / kTile) : 0;
+  const int half = TPP > 1 ? (int)(threadIdx.x / kTile) : 0;
   const int tl = (int)threadIdx.x - half * kTile;  // particle within the tile
   const int i = lb * kTile + tl;
   const bool valid = i < d.n;
@@ -1301,7 +1303,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
     // (sub-list s_lo, then s_hi) so that one prefetch pipeline runs across both
     // (with the halo, threads 0 and 1 of a particle take one sub-list each)
     const bool has_og = !STAGED || half < 2;
-    const int s_lo = STAGED ? min(half, 1) : 0, s_hi = STAGED ? s_lo : 1;
+    const int s_lo = TPP > 1 ? min(half, 1) : 0, s_hi = TPP > 1 ? s_lo : 1;
     const int nbo0 = has_og ? d.n_og[s_lo * np + i] / kOtherBatch : 0;
     const int nbo = nbo0 + (has_og && s_hi != s_lo ? d.n_og[s_hi * np + i] / kOtherBatch : 0);
     const int last_ob = d.K / kOtherBatch - 1;
@@ -1441,6 +1443,27 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
         fx += ex[0]; fy += ex[1]; fz += ex[2];
         if (VIR) for (int q = 0; q < 6; ++q) w[q] += ex[3 + q];
       }
+    } else {
+      for (int q = 0; q < 6; ++q) w[q] = 0.0;
+    }
+  }
+  if constexpr (!STAGED && TPP > 1) {
+    // the thread of sub-list 1 hands its sums (pair forces, virial, DPD terms)
+    // to the thread of sub-list 0, which adds them after its own
+    constexpr int XW = DPD ? 12 : 9;
+    __shared__ double xch[kTile * XW];
+    if (half == 1) {
+      double* ex = xch + tl * XW;
+      ex[0] = fx; ex[1] = fy; ex[2] = fz;
+      if (VIR) for (int q = 0; q < 6; ++q) ex[3 + q] = w[q];
+      if (DPD) { ex[9] = gx; ex[10] = gy; ex[11] = gz; }
+    }
+    __syncthreads();
+    if (half == 0) {
+      const double* ex = xch + tl * XW;
+      fx += ex[0]; fy += ex[1]; fz += ex[2];
+      if (VIR) for (int q = 0; q < 6; ++q) w[q] += ex[3 + q];
+      if (DPD) { gx += ex[9]; gy += ex[10]; gz += ex[11]; }
     } else {
       for (int q = 0; q < 6; ++q) w[q] = 0.0;
     }
@@ -1902,7 +1925,7 @@ static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent
 template <int MODE, bool SAMPLE, bool STAGED>
 static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* so, hipEvent_t e0,
                            hipEvent_t e1) {
-  dim3 g(d.ntiles), b(STAGED ? kForceTPP * kTile : kTile);
+  dim3 g(d.ntiles), b(STAGED ? kForceTPP * kTile : kGlobalTPP * kTile);
   const bool bonds = d.chain_len > 0;
   const bool mixed = d.precision == LE_MIXED;
   if constexpr (!STAGED && MODE != kDpdForce) {
@@ -2034,7 +2057,7 @@ hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const B
 
 template <int MODE, bool SAMPLE, bool STAGED>
 static void launch_force_bs(const Batch& b, const Dev& cfg, hipStream_t s) {
-  const dim3 g = grid_of(b), blk(STAGED ? kForceTPP * kTile : kTile);
+  const dim3 g = grid_of(b), blk(STAGED ? kForceTPP * kTile : kGlobalTPP * kTile);
   const bool bonds = cfg.chain_len > 0;
   if constexpr (!STAGED && MODE != kDpdForce) {
     if (cfg.force_cap > 0.0) {

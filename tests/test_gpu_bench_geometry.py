@@ -281,3 +281,38 @@ def test_nve_energy_with_lazy_lists():
     assert rebuilds > 10 + 10  # lazy rebuilds beyond the 10 forced by the state reads
     assert drift < 2e-3
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["lj_shear_1.0", "lj_shear_0.05", "kg_shear_0.1", "lj_peculiar"])
+def test_lazy_lists_stay_complete(case):
+    """Between rebuilds the forces come from lists built at an earlier state and
+    the positions are not wrapped; the co-moving rebuild criterion must keep
+    every pair within r_c in them.  At checkpoints of a long sheared run, the
+    forces evaluated on the current lists (le_forces, no rebuild) equal the
+    oracle's forces of the same state (read out afterwards, wrapped)."""
+    rng = np.random.default_rng(3)
+    if case.startswith("lj"):
+        sr = 0.5 if case == "lj_peculiar" else float(case.split("_")[-1])
+        w = inputs.lj_workload(n_side=12, shear_rate=sr, seed=5)
+        p = Params(n=w.x.shape[1], box=w.box, shear_rate=sr, seed=5, skin=0.5,
+                   velocity="peculiar" if case == "lj_peculiar" else "lab")
+    else:
+        w = inputs.kg_workload(40, 25, shear_rate=0.1, seed=6)
+        p = Params(n=w.x.shape[1], box=w.box, shear_rate=0.1, seed=6, rc=2 ** (1 / 6), pair="wca",
+                   n_chains=40, chain_len=25, gamma=0.5, dt=0.01, skin=0.6)
+    op = _op(p)
+    sim = Sim(p, w.x, w.u)
+    worst = 0.0
+    r0 = sim.stats()["rebuilds"]
+    for k in range(12):
+        sim.step(int(rng.integers(17, 61)))
+        F, _ = sim.forces()
+        x, u, f, st = sim.state()
+        Delta = O.offset(st, p.dt, p.shear_rate, p.box[0], p.box[1])
+        Fr, _, _ = O.forces(x, Delta, op, 1)
+        worst = max(worst, e_F(F, Fr))
+    rebuilds = sim.stats()["rebuilds"] - r0 - 12  # without the 12 forced by the state reads
+    _log(f"{case}: worst e_F on lazy lists {worst:.3e}, rebuilds by the criterion {rebuilds}")
+    assert worst <= 1e-10
+    assert rebuilds >= 3
+    sim.close()
