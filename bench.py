@@ -199,8 +199,9 @@ def kernel_hash():
 
 def read_traffic(name, skin):
     """HBM bytes per launch of a kernel from a committed rocprofv3 PMC summary
-    (profiles/<name>.md), or None if it was taken on another kernel source or
-    at another skin (other list lengths, other traffic)."""
+    (profiles/<name>.md: one `hbm_bytes_per_launch@<skin>` line per profiled skin),
+    or None if it was taken on another kernel source or at another skin (other
+    list lengths, other traffic)."""
     path = os.path.join(ROOT, "profiles", name + ".md")
     if not os.path.exists(path):
         return None
@@ -212,12 +213,14 @@ def read_traffic(name, skin):
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel source sha256 prefix") != kernel_hash():
         return None
-    try:
-        if abs(float(vals["skin"]) - float(skin)) > 1e-9:
-            return None
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    for k, v in vals.items():
+        if k.startswith("hbm_bytes_per_launch@"):
+            try:
+                if abs(float(k.split("@", 1)[1]) - float(skin)) <= 1e-6:
+                    return float(v)
+            except ValueError:
+                continue
+    return None
 
 
 def roofline_of(r, kind, precision, skin, dpd=False):
