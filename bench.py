@@ -406,6 +406,41 @@ def c5_sweep(scale=0.1, steps=30000, warmup=1000, seed=51, dt=0.005):
     return out
 
 
+def batch_probe(count=64, steps=500, alone=8):
+    """The first `count` requests of the serving trace (FP64, cell-filling skin of 0.4,
+    LDS-halo layout) created together and advanced as one batch with le_step_batch,
+    then `alone` of them one by one with le_step: ms per step and particle-steps/s."""
+    import torch
+    from paper_2109_11083_amd.serve import request_params, sweep_trace
+    from paper_2109_11083_amd.sim import Sim, step_batch
+    trace = sweep_trace(count=count, precision="fp64", burst=True, skin=0.4, tune=1)
+    reqs = [request_params(r) for r in trace]
+    stream = torch.cuda.Stream()
+    sims = [Sim(p, w.x, w.u, stream=stream) for w, p in reqs]
+    ntot = sum(s.params.n for s in sims)
+    step_batch(sims, 100)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    step_batch(sims, steps)
+    stream.synchronize()
+    t1 = time.perf_counter()
+    out = dict(members=count, n_total=ntot, steps=steps, ms_per_step=1e3 * (t1 - t0) / steps,
+               value=ntot * steps / (t1 - t0), alone=[])
+    for s in sims:
+        s.close()
+    for w, p in reqs[:alone]:
+        s = Sim(p, w.x, w.u)
+        s.step(100)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        out["alone"].append(dict(n=p.n, ms_per_step=1e3 * dt / steps, value=p.n * steps / dt))
+        s.close()
+    return out
+
+
 def host_info():
     info = dict(nproc=os.cpu_count())
     try:
@@ -494,6 +529,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration) and exit")
+    ap.add_argument("--batch-probe", type=int, default=0, metavar="COUNT",
+                    help="only advance the first COUNT serving requests as one batch (then 8 alone), "
+                         "print their timings and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -504,6 +542,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
         copy_probe()
+        return
+    if args.batch_probe:
+        print(json.dumps(batch_probe(args.batch_probe, steps=args.steps if args.steps != 10000 else 500)),
+              flush=True)
         return
     kg = args.workload == "kg"
     sr = args.shear_rate if args.shear_rate is not None else (0.01 if kg else 0.1)

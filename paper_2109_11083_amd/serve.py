@@ -146,7 +146,7 @@ class Server:
     graphs: replay captured chunks; mode: "batched" or "streams" (see module)."""
 
     def __init__(self, hbm_budget=16 << 30, max_active=64, chunk=500, ahead=2, keep_state=False,
-                 graphs=True, mode="batched"):
+                 graphs=True, mode="batched", graph_steps=100):
         assert mode in ("batched", "streams")
         self.hbm_budget = hbm_budget
         self.max_active = max_active
@@ -155,6 +155,7 @@ class Server:
         self.keep_state = keep_state
         self.graphs = graphs
         self.mode = mode
+        self.graph_steps = graph_steps  # steps per captured batch graph (replayed chunk/graph_steps times)
 
     # ------------------------------------------------------------ shared
     def _finish(self, a: _Active, now: float) -> Result:
@@ -209,27 +210,32 @@ class Server:
 
     # ------------------------------------------------------------ batched
     def _enqueue_batch(self, members, k, se, stream, state):
-        """One chunk of k steps for every member: a replay of the cached batch graph
-        when the batch is the one it was captured for, else le_step_batch (and a
-        capture for the next chunk of the same batch)."""
-        key = (tuple(id(a) for a in members), k)
+        """One chunk of k steps for every member: replays of the cached batch graph
+        (graph_steps steps each) when the batch is the one it was captured for, else a
+        capture for this batch first; le_step_batch when k is not a whole number of
+        graph chunks.  A short graph keeps the capture cost small, since the batch
+        changes with every arrival and departure."""
+        g_steps = min(self.graph_steps, k)
+        key = (tuple(id(a) for a in members), g_steps)
         rows = [a.issued // se for a in members]
         keep = None
-        if self.graphs and k % 2 == 0 and k % se == 0:
+        if self.graphs and g_steps % 2 == 0 and g_steps % se == 0 and k % g_steps == 0:
             if state.get("key") != key:
                 old = state.pop("graph", None)
                 if old is not None:
                     state.setdefault("retired", []).append(old)
                 with torch.cuda.stream(stream):
-                    grings = [torch.zeros((k // se, 6), dtype=torch.float64, device="cuda")
+                    grings = [torch.zeros((g_steps // se, 6), dtype=torch.float64, device="cuda")
                               for _ in members]
-                state["graph"] = BatchGraph([a.sim for a in members], k, sample_every=se, rings=grings)
+                state["graph"] = BatchGraph([a.sim for a in members], g_steps, sample_every=se, rings=grings)
                 state["key"] = key
             g = state["graph"]
-            g.launch()
-            with torch.cuda.stream(stream):
-                for a, r0, gr in zip(members, rows, g.rings):
-                    a.ring[r0:r0 + gr.shape[0]].copy_(gr)
+            for rep in range(k // g_steps):
+                g.launch()
+                with torch.cuda.stream(stream):
+                    for a, r0, gr in zip(members, rows, g.rings):
+                        r1 = r0 + rep * gr.shape[0]
+                        a.ring[r1:r1 + gr.shape[0]].copy_(gr)
             keep = g
         else:
             rings = [a.ring[r0:] for a, r0 in zip(members, rows)]
