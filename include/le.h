@@ -107,7 +107,7 @@ typedef int32_t le_status;
 /* Parameters of one simulation (Sections 2.1, 2.2, 2.4).  All 8-byte fields
  * come first so that the layout has no padding. */
 typedef struct le_params {
-  int64_t n;           /* number of particles (>= 2)                               */
+  int64_t n;           /* number of particles (2 .. 16,777,214)                    */
   double box[3];       /* L_x, L_y, L_z                                             */
   double shear_rate;   /* gamma_dot of Eq. shear-rate (any sign; 0 = equilibrium)   */
   double dt;           /* time step (> 0)                                           */

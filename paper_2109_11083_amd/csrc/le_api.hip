@@ -58,7 +58,8 @@ struct Geometry {
 
 le_status validate(const le_params* p, Geometry* g) {
   if (!p) return LE_E_ARG;
-  if (p->n < 2 || p->n > (int64_t)0x7fffffff / 4) return LE_E_ARG;
+  // slots (n + 1 with the sentinel) share a 32-bit list entry with a 7-bit image code
+  if (p->n < 2 || p->n >= ((int64_t)1 << kSlotBits) - 1) return LE_E_ARG;
   for (int a = 0; a < 3; ++a)
     if (!(p->box[a] > 0.0) || !isfinite(p->box[a])) return LE_E_ARG;
   if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->kT >= 0.0) || !(p->gamma >= 0.0)) return LE_E_ARG;
@@ -152,7 +153,6 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
   t.nl16 = (uint16_t*)take((size_t)g.K * 2 * np * sizeof(uint16_t));
   t.nlo = (uint32_t*)take((size_t)g.K * 2 * np * sizeof(uint32_t));
-  t.nlc = (uint8_t*)take((size_t)g.K * 2 * np);
   t.n_plain = (int32_t*)take(2 * np * sizeof(int32_t));
   t.n_og = (int32_t*)take(2 * np * sizeof(int32_t));
   t.halo_slot = (int32_t*)take((size_t)g.nblocks * kHalo * sizeof(int32_t));
@@ -177,7 +177,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
     d->vt = t.vt;
     d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->bucket = t.bucket;
     d->cell_count = t.cell_count; d->cell_start = t.cell_start;
-    d->nl16 = t.nl16; d->nlo = t.nlo; d->nlc = t.nlc;
+    d->nl16 = t.nl16; d->nlo = t.nlo;
     d->n_plain = t.n_plain; d->n_og = t.n_og;
     d->halo_slot = t.halo_slot; d->halo_code = t.halo_code; d->tile_nstage = t.tile_nstage;
     d->bond = t.bond;

@@ -113,15 +113,14 @@ struct Dev {
   // Neighbour lists: two sub-lists per particle (v = h * np + i, h = 0, 1,
   // the two halves of each stencil range).  Entry k of sub-list v lives in a
   // block of consecutive entries: blocks of 8 (one 16-byte load) for nl16, of
-  // 4 for nlo/nlc; block b of sub-lists v, v+1, ... is contiguous.
+  // 4 for nlo; block b of sub-lists v, v+1, ... is contiguous.
   //   nl16  partners staged in the tile's LDS halo (any image): LDS index,
   //         element k at ((k/8)*np2 + v)*8 + k%8
-  //   nlo   partners not staged: slot in global memory, element k at
+  //   nlo   partners not staged: slot in global memory in the low kSlotBits
+  //         bits, image code (pack_img) above them; element k at
   //         ((k/4)*np2 + v)*4 + k%4
-  //   nlc   image code of each nlo entry, same layout (bytes)
   uint16_t* nl16;
   uint32_t* nlo;
-  uint8_t* nlc;
   int32_t* n_plain;                // [np2] staged entries per sub-list, multiple of kPlainBatch
   int32_t* n_og;                   // [np2] global entries per sub-list, multiple of kOtherBatch
   int32_t* halo_slot;              // [ntiles][kHalo] slot staged at each LDS position
@@ -153,6 +152,13 @@ struct Batch {
 struct BatchOut {
   double* ptr[kMaxBatch];  // per-simulation output (the stress sample of this step)
 };
+
+// Entries of the lists of global slots: slot | code << kSlotBits (codes use 7 bits).
+constexpr int kSlotBits = 24;
+constexpr uint32_t kSlotMask = (1u << kSlotBits) - 1u;
+__host__ __device__ inline uint32_t og_entry(uint32_t slot, uint8_t code) {
+  return slot | ((uint32_t)code << kSlotBits);
+}
 
 // Image code of an imaged neighbour: sx in [-3, 3], sy and sz in [-1, 1].
 __host__ __device__ inline uint8_t pack_img(int sx, int sy, int sz) {

@@ -560,7 +560,6 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   auto& lbuf = sr.ring;
   // with GL: the ring of slots and image codes of lists of global slots
   __shared__ __align__(16) uint32_t gslot[GL ? 2 * kTile : 1][kOtherBatch];
-  __shared__ __align__(4) uint8_t gcode[GL ? 2 * kTile : 1][kOtherBatch];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
@@ -746,21 +745,20 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   const float tlo = d.nb_lo, thi = d.nb_hi;
   const size_t hbase = (size_t)tile * kHalo;
   int npl = 0, nog = 0;
-  // one global-list entry: with GL into the lane's ring, a completed block of
-  // four leaving as one 16-byte and one 4-byte store; otherwise (rows beyond
-  // the halo of a halo-layout list) straight to global memory
+  // one global-list entry (slot and image code in one word): with GL into the
+  // lane's ring, a completed block of four leaving as one 16-byte store;
+  // otherwise (rows beyond the halo of a halo-layout list) straight to global
+  // memory
   auto og_append = [&](uint32_t slot, uint8_t code) {
     if constexpr (GL) {
-      gslot[threadIdx.x][nog & 3] = slot;
-      gcode[threadIdx.x][nog & 3] = code;
+      gslot[threadIdx.x][nog & 3] = og_entry(slot, code);
       ++nog;
       if ((nog & 3) == 0 && nog <= K) {
         const size_t b = (size_t)((nog >> 2) - 1) * np2 + v;
         reinterpret_cast<uint4*>(d.nlo)[b] = *reinterpret_cast<const uint4*>(gslot[threadIdx.x]);
-        reinterpret_cast<uint32_t*>(d.nlc)[b] = *reinterpret_cast<const uint32_t*>(gcode[threadIdx.x]);
       }
     } else {
-      if (nog < K) { d.nlo[idx4(nog, v, np2)] = slot; d.nlc[idx4(nog, v, np2)] = code; }
+      if (nog < K) d.nlo[idx4(nog, v, np2)] = og_entry(slot, code);
       ++nog;
     }
   };
@@ -1313,32 +1311,32 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
       return (size_t)blk * np2 + (size_t)(first ? s_lo : s_hi) * np + i;
     };
     const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.nlo);
-    const uint32_t* __restrict__ c4 = reinterpret_cast<const uint32_t*>(d.nlc);
     // GB blocks of 4 per round: one for the plain global layout (fewer
     // gathers in flight leave room for more waves: KG 49 -> 48 us), two with
     // the halo's remainder pieces and with DPD (one block: 138 -> 195 us)
     constexpr int GB = (STAGED || DPD) ? 2 : 1;
     uint4 jn[GB];
-    uint32_t cn[GB];
 #pragma unroll
-    for (int k = 0; k < GB; ++k) { jn[k] = l4[ooff(k)]; cn[k] = c4[ooff(k)]; }
+    for (int k = 0; k < GB; ++k) jn[k] = l4[ooff(k)];
     {
     for (int b = 0; b < nbo; b += GB) {
-      uint4 jq[GB];
-      uint32_t cq[GB];
-      uint32_t sl[4 * GB];
+      // slots, and the four image codes of a block repacked into one word
+      // (fewer live registers while the gathers are in flight)
+      uint32_t sl[4 * GB], cq[GB];
 #pragma unroll
       for (int k = 0; k < GB; ++k) {
-        jq[k] = jn[k];
-        cq[k] = cn[k];
-        const size_t o = ooff(b + GB + k);
-        jn[k] = l4[o];
-        cn[k] = c4[o];
+        const uint4 jq = jn[k];
+        jn[k] = l4[ooff(b + GB + k)];
         const bool in = b + k < nbo;  // the entries of this block are the list's
-        sl[4 * k] = in ? jq[k].x : (uint32_t)d.n;
-        sl[4 * k + 1] = in ? jq[k].y : (uint32_t)d.n;
-        sl[4 * k + 2] = in ? jq[k].z : (uint32_t)d.n;
-        sl[4 * k + 3] = in ? jq[k].w : (uint32_t)d.n;
+        sl[4 * k] = (in ? jq.x : (uint32_t)d.n) & kSlotMask;
+        sl[4 * k + 1] = (in ? jq.y : (uint32_t)d.n) & kSlotMask;
+        sl[4 * k + 2] = (in ? jq.z : (uint32_t)d.n) & kSlotMask;
+        sl[4 * k + 3] = (in ? jq.w : (uint32_t)d.n) & kSlotMask;
+        cq[k] = (jq.x >> kSlotBits) | ((jq.y >> kSlotBits) << 8) | ((jq.z >> kSlotBits) << 16) |
+                (jq.w & ~kSlotMask);
+        // opaque to the optimiser, so that the codes stay one packed word
+        // instead of being unpacked from the entries ahead of their use
+        asm("" : "+v"(cq[k]));
       }
       double4 pj[4 * GB];
 #pragma unroll
@@ -1348,6 +1346,9 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
       if (DPD) {
 #pragma unroll
         for (int u = 0; u < 4 * GB; ++u) vj[u] = VT[sl[u]];
+        // every gather of the round issued before the first use (without this
+        // fence the scheduler sinks each to its use, one wait per gather)
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int u = 0; u < 4 * GB; ++u) {
@@ -1540,9 +1541,14 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
   }
 }
 
+// The float64 DPD form is held to 3 waves per SIMD (at most 168 VGPRs): it
+// is latency-bound, and 2 waves made it 1.45x slower.
+template <int MODE, bool MIXED, bool STAGED>
+constexpr int force_waves() { return MODE == kDpdForce && !MIXED && !STAGED ? 3 : 1; }
+
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
-__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force(Dev d, double* __restrict__ f_out,
-                                                     double* __restrict__ sample_out) {
+__global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile)
+    k_force(Dev d, double* __restrict__ f_out, double* __restrict__ sample_out) {
   (void)sample_out;
   force_body<MODE, MIXED, BONDS, SAMPLE, STAGED, CAP>(d, xcd_block(d.ntiles), f_out);
 }
@@ -1850,7 +1856,7 @@ __global__ void k_pairs_out(Dev d, int64_t* pairs, int64_t cap, unsigned long lo
       if (h == kHalo) continue;
       slot = hs[h];
     } else {
-      slot = (int)d.nlo[idx4(k - npl, v, np2)];
+      slot = (int)(d.nlo[idx4(k - npl, v, np2)] & kSlotMask);
       if (slot == d.n) continue;
     }
     int tj = tag[slot];

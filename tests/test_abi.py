@@ -122,3 +122,13 @@ def test_force_cap_is_validated_on_the_host():
         with pytest.raises(B.LeError) as e:
             B.le_workspace_bytes(bad.to_c())
         assert e.value.code == B.LE_E_ARG
+
+
+def test_particle_count_fits_the_list_entries():
+    """A global-list entry holds a slot (0..n, n the sentinel) in 24 bits next
+    to a 7-bit image code, so n is at most 2^24 - 2."""
+    assert B.le_workspace_bytes(_lj(n=2**24 - 2, L=200.0).to_c()) > 0
+    for n in (2**24 - 1, 2**24):
+        with pytest.raises(B.LeError) as e:
+            B.le_workspace_bytes(_lj(n=n, L=200.0).to_c())
+        assert e.value.code == B.LE_E_ARG
