@@ -468,12 +468,13 @@ __global__ void __launch_bounds__(kBlock) k_permute_b(Batch b) {
 // span a few cell rows.  For every covered row r, offset (dy, dz) and x-image
 // sx, the cells the tile's stencils can reach in the neighbouring row form a
 // contiguous slot range (a "piece").  The pieces are staged into LDS in a
-// fixed order while they fit (kHalo positions); halo_slot records the slot
-// at every LDS position so that the force kernel can restage the same halo
-// each step.  Pairs whose partner is staged store its LDS index (16 bits
-// without image, 32 bits + code with one); pairs into unstaged pieces store
-// the partner's slot.  Lists are padded with sentinels (LDS index kHalo,
-// slot n) to whole batches.
+// fixed order while they fit (kHalo positions).  With the halo layout,
+// halo_slot / halo_code record the slot and image of every LDS position so
+// that the force kernel can restage the same halo each step; the global
+// layout keeps that table in LDS for the search alone.  Pairs whose partner
+// is staged without image store its LDS index (16 bits, halo layout); the
+// others store the partner's slot and image code in one 32-bit word.  Lists
+// are padded with sentinels (LDS index kHalo, slot n) to whole batches.
 
 struct TileGeom {
   int row_first, nrows, staged_ok;
@@ -511,7 +512,7 @@ constexpr int kWaves = kTile / 64;
 // Tile halo pieces: for each covered row r of the tile, offset (dy, dz) and
 // x-image sx, the slot range of the neighbouring row reached by the tile.
 // Fills the piece tables, assigns LDS offsets in a fixed order while they
-// fit, stages the positions and records halo_slot.  Called by all threads.
+// fit, stages the positions and records their slots.  Called by all threads.
 struct Pieces {
   int start[kMaxRows * 9][kPieces];
   int count[kMaxRows * 9][kPieces];
@@ -558,8 +559,11 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   };
   __shared__ __align__(16) StageRing sr;
   auto& lbuf = sr.ring;
-  // with GL: the ring of slots and image codes of lists of global slots
+  // with GL: the ring of list entries (slot and image code) of lists of
+  // global slots, and the entry of every staged position (the lists need no
+  // halo tables in global memory then)
   __shared__ __align__(16) uint32_t gslot[GL ? 2 * kTile : 1][kOtherBatch];
+  __shared__ uint32_t hent[GL ? HALO + 8 : 1];
   __shared__ int skip;
   Ctrl* c = d.ctrl;
   if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
@@ -713,7 +717,9 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
         hx[hw] = (float)((pj[u].x + ((double)sy * Delta + (double)sx * d.Lx)) - org.x);
         hy[hw] = (float)((pj[u].y + (double)sy * d.Ly) - org.y);
         hz[hw] = (float)((pj[u].z + (double)sz * d.Lz) - org.z);
-        if (h < tot) {
+        if constexpr (GL) {
+          hent[hw] = og_entry((uint32_t)slot[u], (uint8_t)code[u]);
+        } else if (h < tot) {
           d.halo_slot[(size_t)tile * kHalo + h] = slot[u];
           d.halo_code[(size_t)tile * kHalo + h] = (uint8_t)code[u];
         }
@@ -745,20 +751,20 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   const float tlo = d.nb_lo, thi = d.nb_hi;
   const size_t hbase = (size_t)tile * kHalo;
   int npl = 0, nog = 0;
-  // one global-list entry (slot and image code in one word): with GL into the
-  // lane's ring, a completed block of four leaving as one 16-byte store;
-  // otherwise (rows beyond the halo of a halo-layout list) straight to global
-  // memory
-  auto og_append = [&](uint32_t slot, uint8_t code) {
+  // one global-list entry (og_entry: slot and image code in one word): with
+  // GL into the lane's ring, a completed block of four leaving as one 16-byte
+  // store; otherwise (rows beyond the halo of a halo-layout list) straight to
+  // global memory
+  auto og_append = [&](uint32_t e) {
     if constexpr (GL) {
-      gslot[threadIdx.x][nog & 3] = og_entry(slot, code);
+      gslot[threadIdx.x][nog & 3] = e;
       ++nog;
       if ((nog & 3) == 0 && nog <= K) {
         const size_t b = (size_t)((nog >> 2) - 1) * np2 + v;
         reinterpret_cast<uint4*>(d.nlo)[b] = *reinterpret_cast<const uint4*>(gslot[threadIdx.x]);
       }
     } else {
-      if (nog < K) d.nlo[idx4(nog, v, np2)] = og_entry(slot, code);
+      if (nog < K) d.nlo[idx4(nog, v, np2)] = e;
       ++nog;
     }
   };
@@ -814,10 +820,19 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
         const int u = __builtin_ctz(m_band);
         m_band &= m_band - 1u;
         const int h = h0 + u;
+        int q2;
+        uint8_t c2;
+        if constexpr (GL) {
+          q2 = (int)(hent[h] & kSlotMask);
+          c2 = (uint8_t)(hent[h] >> kSlotBits);
+        } else {
+          q2 = d.halo_slot[hbase + h];
+          c2 = d.halo_code[hbase + h];
+        }
         int sx2, sy2, sz2;
-        unpack_img(d.halo_code[hbase + h], sx2, sy2, sz2);
-        if (in_list_exact(d, pi, P[d.halo_slot[hbase + h]], (double)sx2 * d.Lx, (double)sy2 * d.Ly,
-                          (double)sz2 * d.Lz, (double)sy2 * Delta))
+        unpack_img(c2, sx2, sy2, sz2);
+        if (in_list_exact(d, pi, P[q2], (double)sx2 * d.Lx, (double)sy2 * d.Ly, (double)sz2 * d.Lz,
+                          (double)sy2 * Delta))
           m_in |= 1u << u;
       }
       if constexpr (GL) {
@@ -825,7 +840,7 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
         while (m_in) {
           const int u = __builtin_ctz(m_in);
           m_in &= m_in - 1u;
-          og_append((uint32_t)d.halo_slot[hbase + h0 + u], d.halo_code[hbase + h0 + u]);
+          og_append(hent[h0 + u]);
         }
       } else {
         // append the accepted LDS indices into a ring of 16 per lane: every
@@ -861,7 +876,7 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
           if (plain && q == i) continue;
           if (in_list_exact(d, pi, P[q], (double)sx * d.Lx, (double)sy * d.Ly, (double)sz * d.Lz,
                             (double)sy * Delta)) {
-            og_append((uint32_t)q, code);
+            og_append(og_entry((uint32_t)q, code));
           }
         }
       }
@@ -900,7 +915,7 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
       }
     }
     const uint8_t zero = pack_img(0, 0, 0);
-    while (nog < nog_p) og_append((uint32_t)n, zero);  // sentinel entries up to a whole block
+    while (nog < nog_p) og_append(og_entry((uint32_t)n, zero));  // sentinel entries up to a whole block
   }
   d.n_plain[v] = npl_p;
   d.n_og[v] = nog_p;
