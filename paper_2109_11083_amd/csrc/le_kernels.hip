@@ -203,8 +203,12 @@ __device__ __forceinline__ void rebuild_adopt(Ctrl& c) {
   c.n_rebuilds += 1;
 }
 
+// (both words read unconditionally, so that the two loads overlap: this is
+// all an empty launch of the chain does)
 __device__ __forceinline__ bool rebuild_off(const Dev& d) {
-  return d.flags->status != 0 || !d.ctrl->rebuild;
+  const int status = d.flags->status;
+  const int rebuild = d.ctrl->rebuild;
+  return (status != 0) | (rebuild == 0);
 }
 
 // (1) Reads control copy d.ctrl and writes the next one (block 0).  With
@@ -1301,8 +1305,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         double dx = pi.x - xj[u], dy = pi.y - yj[u], dz = pi.z - zj[u];
-        double r2 = dx * dx + dy * dy;
-        r2 = r2 + dz * dz;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         add_pair<VIR>(lj_masked<MIXED>(r2, rc2, sig2, eps24), dx, dy, dz, fx, fy, fz, w);
       }
       v0 = v1;
@@ -1373,8 +1376,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
         double dy = (pi.y - pj[u].y) - (double)sy * d.Ly;
         double dx = ((pi.x - pj[u].x) - (double)sy * Delta) - (double)sx * d.Lx;
         double dz = (pi.z - pj[u].z) - (double)sz * d.Lz;
-        double r2 = dx * dx + dy * dy;
-        r2 = r2 + dz * dz;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         add_pair<VIR>(lj_masked<MIXED, CAP>(r2, rc2, sig2, eps24, d.force_cap), dx, dy, dz, fx, fy, fz, w);
         if (DPD) {
           // the image s_y boxes up streams faster by s_y gamma_dot L_y
