@@ -54,6 +54,7 @@ struct Geometry {
   int64_t np;
   int32_t nblocks;
   int32_t bcap;
+  int32_t sp_cells, sp_blocks;  // scan-and-permute pass: cells per block, blocks
 };
 
 le_status validate(const le_params* p, Geometry* g) {
@@ -119,6 +120,13 @@ le_status validate(const le_params* p, Geometry* g) {
     g->bcap = ((int32_t)ceil(cap) + 7) / 8 * 8;
   }
   g->nblocks = (int32_t)((p->n + kTile - 1) / kTile);
+  {
+    // about kSortParticles particles per block of the scan-and-permute pass
+    const int64_t ncell = (int64_t)g->nc[0] * g->nc[1] * g->nc[2];
+    const double mean = (double)p->n / (double)ncell;
+    g->sp_cells = (int32_t)fmin(fmax(ceil(kSortParticles / mean), 1.0), (double)kBlock);
+    g->sp_blocks = (int32_t)((ncell + g->sp_cells - 1) / g->sp_cells);
+  }
   return LE_OK;
 }
 
@@ -137,7 +145,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   t.ctrl = (Ctrl*)take(2 * sizeof(Ctrl));
   t.flags = (Flags*)take(sizeof(Flags));
   t.vmax = (unsigned long long*)take(2 * kSlots * kLineU64 * sizeof(unsigned long long));
-  t.scan_status = (unsigned long long*)take(((ncell + kScanTile - 1) / kScanTile) * sizeof(unsigned long long));
+  t.scan_status = (unsigned long long*)take((size_t)g.sp_blocks * sizeof(unsigned long long));
   for (int b = 0; b < 2; ++b) {
     t.pos[b] = (double*)take(4 * np * sizeof(double));
     t.vel[b] = (double*)take(3 * np * sizeof(double));
@@ -146,8 +154,6 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   }
   t.vt = (p->thermostat == LE_THERMO_DPD) ? (double*)take(4 * np * sizeof(double)) : nullptr;
   t.slot_of_tag = (int32_t*)take(np * sizeof(int32_t));
-  t.cell_of = (int32_t*)take(np * sizeof(int32_t));
-  t.rank = (int32_t*)take(np * sizeof(int32_t));
   t.bucket = (int32_t*)take(ncell * (size_t)g.bcap * sizeof(int32_t));
   t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
@@ -175,7 +181,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
       d->pos[b] = t.pos[b]; d->vel[b] = t.vel[b]; d->frc[b] = t.frc[b]; d->tag[b] = t.tag[b];
     }
     d->vt = t.vt;
-    d->slot_of_tag = t.slot_of_tag; d->cell_of = t.cell_of; d->rank = t.rank; d->bucket = t.bucket;
+    d->slot_of_tag = t.slot_of_tag; d->bucket = t.bucket;
     d->cell_count = t.cell_count; d->cell_start = t.cell_start;
     d->nl16 = t.nl16; d->nlo = t.nlo;
     d->n_plain = t.n_plain; d->n_og = t.n_og;
@@ -262,6 +268,8 @@ void fill_geometry(const le_params* p, const Geometry& g, Dev* d) {
   d->nblocks = g.nblocks;
   d->ntiles = g.nblocks;
   d->bcap = g.bcap;
+  d->sp_cells = g.sp_cells;
+  d->sp_blocks = g.sp_blocks;
   {
     // LDS halo at force time when partners per particle clearly outnumber the
     // positions a tile must stage per particle (strip tile of kTile particles:
@@ -396,7 +404,7 @@ void fill_group(BatchGroup& g) {
       g.par[v].start[k] = op; g.scan[v].start[k] = os; g.tile[v].start[k] = ot; g.one[v].start[k] = (int32_t)k;
       g.par[v].dev[k] = g.scan[v].dev[k] = g.tile[v].dev[k] = g.one[v].dev[k] = dv;
       op += (s->d.n + kBlock - 1) / kBlock;
-      os += (s->d.ncell + kScanTile - 1) / kScanTile;
+      os += s->d.sp_blocks;
       ot += s->d.ntiles;
     }
     const size_t m = g.sims.size();
@@ -443,7 +451,7 @@ le_status step_batch(std::vector<BatchGroup>& groups, hipStream_t q, int64_t nst
   for (BatchGroup& g : groups)
     if (st == LE_OK) st = hip_check(launch_kick_drift_b(g.par[v], q));
   for (BatchGroup& g : groups)
-    if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.par[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+    if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
   v ^= 1;
   int64_t ns = 0;
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
@@ -467,7 +475,7 @@ le_status step_batch(std::vector<BatchGroup>& groups, hipStream_t q, int64_t nst
     if (sample) ++ns;
     if (st == LE_OK && !last) {
       for (BatchGroup& g : groups)
-        if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.par[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+        if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
       v ^= 1;
     }
   }

@@ -22,12 +22,11 @@ constexpr int kMaxRows = 3;        // cell rows a tile may span and still be sta
 constexpr int kPieces = 4;         // x-image pieces per (row, dy, dz) of a tile
 constexpr int kPlainBatch = 8;     // padding of the plain list (LDS gathers in flight)
 constexpr int kOtherBatch = 4;     // padding of the imaged / global lists
-constexpr int kScanBlock = 1024;   // threads per block of the cell-count scan
 constexpr int kStressComps = 12;   // 6 kinetic + 6 virial partial sums per block
 constexpr int kSlots = 64;         // words (one per 128-byte line) a block maximum is spread over
 constexpr int kLineInts = 32;      // 32-bit words per 128-byte line
 constexpr int kLineU64 = 16;       // 64-bit words per 128-byte line
-constexpr int kScanTile = 8 * kScanBlock;  // cells per block of the cell-count scan
+constexpr int kSortParticles = 512;  // particles per block of the scan-and-permute pass (on average)
 
 // Mutable per-simulation scalars that live on the device so that a step
 // never needs the host: step counter, offset, rebuild bookkeeping.  Two
@@ -104,8 +103,6 @@ struct Dev {
                                    // packed before each force evaluation (one gather per partner)
   int32_t* tag[2];                 // slot -> tag
   int32_t* slot_of_tag;            // tag -> slot
-  int32_t* cell_of;                // cell of each slot (binning pass)
-  int32_t* rank;                   // arrival rank inside the cell (binning pass)
   int32_t bcap;                    // bucket capacity per cell
   int32_t* bucket;                 // [ncell][bcap] tags binned into each cell (arrival order)
   int32_t* cell_count;             // [ncell]
@@ -136,7 +133,8 @@ struct Dev {
   // words of kLineU64 stride; two arrays alternate with the control copies
   unsigned long long* vmax;
   unsigned long long* vmax_other;  // the speed-bound slots paired with ctrl_other
-  unsigned long long* scan_status; // [ceil(ncell / kScanTile)] look-back words of the cell scan
+  unsigned long long* scan_status; // [sp_blocks] look-back words of the cell scan
+  int32_t sp_cells, sp_blocks;     // cells per block of the scan-and-permute pass, and its blocks
   Flags* flags;
 };
 
@@ -203,13 +201,13 @@ hipError_t launch_status_out(const Dev& d, hipStream_t s, int32_t* out);
 // Batched launchers: one launch over the blocks of every simulation of a
 // batch (all of one kernel configuration, given by `cfg`, the host copy of any
 // member's descriptor).  Batches by block kind: `par` one block per kBlock
-// particles, `scan` one per kScanTile cells, `tile` one per kTile particles,
+// particles, `scan` one per sp_cells cells, `tile` one per kTile particles,
 // `one` one block per simulation; `cur` and `nxt` name the descriptors of the
 // current and the other control copy.
 hipError_t launch_store_dev(const Dev& a, const Dev& b, Dev* dst, hipStream_t s);
 hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s);
-hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& par_nxt,
-                            const Batch& tile_nxt, const Dev& cfg, hipStream_t s);
+hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& tile_nxt,
+                            const Dev& cfg, hipStream_t s);
 hipError_t launch_force_b(const Batch& tile_cur, const Batch& par_cur, const Dev& cfg, hipStream_t s,
                           ForceMode mode, bool sample);
 hipError_t launch_integrate_b(const Batch& tile_cur, hipStream_t s, bool last, bool sample);

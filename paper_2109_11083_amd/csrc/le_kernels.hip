@@ -135,6 +135,7 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
       d.frc[0][a * np + i] = f0 ? f0[a * n + i] : 0.0;
     }
     d.tag[0][i] = i;
+    d.slot_of_tag[i] = i;
   }
   if (i == 0) {
     // far-away sentinel at slot n pads neighbour batches: r^2 ~ 1e200 never passes a cutoff
@@ -162,9 +163,10 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
 }
 
 // ------------------------------------------------------------- rebuild
-// Four kernels, each an empty launch unless the lists are rebuilt for the
+// Three kernels, each an empty launch unless the lists are rebuilt for the
 // current state: (1) advance the step and decide, then crossing + wrap + bin,
-// (2) cell-count scan, (3) rank by tag + permute, (4) neighbour lists.
+// (2) cell-count scan and, block by block, rank by tag + permute, (3)
+// neighbour lists.
 
 // Advance the step counter and the offset, adopt the drifted positions, and
 // decide whether the neighbour lists must be rebuilt before the next force
@@ -214,8 +216,8 @@ __device__ __forceinline__ bool rebuild_off(const Dev& d) {
 // (1) Reads control copy d.ctrl and writes the next one (block 0).  With
 // `control` the step is advanced first (after a drift).  On a rebuild:
 // boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
-// x and z in place, then each particle's cell and its arrival rank there.
-// Runs of equal cells within a wave take one atomic per run.
+// x and z in place, then each particle's tag goes into its cell's bucket at
+// its arrival rank.  Runs of equal cells within a wave take one atomic per run.
 __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict__ next,
                                                  unsigned long long* __restrict__ next_vmax, int force,
                                                  int control, int bid) {
@@ -238,11 +240,8 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
     }
     if (bid == 0) {
       if (threadIdx.x < kSlots) next_vmax[threadIdx.x * kLineU64] = 0ull;
-      if (rb) {
+      if (rb)
         for (int k = threadIdx.x; k < kSlots * kLineInts; k += 64) d.flags->max_nb_slot[k] = 0;
-        const int nst = (d.ncell + kScanTile - 1) / kScanTile;
-        for (int k = threadIdx.x; k < nst; k += 64) d.scan_status[k] = 0ull;
-      }
       if (threadIdx.x == 0) {
         Ctrl o = c;
         o.rebuild = 0;
@@ -254,6 +253,8 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
   __syncthreads();
   if (!go) return;
   const int i = bid * kBlock + threadIdx.x;
+  // the look-back words of the scan start cleared (spread over the blocks)
+  for (int k = i; k < d.sp_blocks; k += ((d.n + kBlock - 1) / kBlock) * kBlock) d.scan_status[k] = 0ull;
   const int np = d.np;
   int cell = -1;
   if (i < d.n) {
@@ -283,7 +284,6 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
     int iy = cell_index(y, d.inv_ly, d.ny);
     int iz = cell_index(z, d.inv_lz, d.nz);
     cell = (iz * d.ny + iy) * d.nx + ix;
-    d.cell_of[i] = cell;
   }
   // runs of equal cells among consecutive lanes share one atomic
   const int lane = threadIdx.x & 63;
@@ -298,7 +298,6 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
   base = __shfl(base, run0, 64);
   if (cell >= 0) {
     const int r = base + (lane - run0);
-    d.rank[i] = r;
     if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = d.tag[sc.aux_cur][i];
     else latch(d.flags, LE_E_CAPACITY);
   }
@@ -319,33 +318,37 @@ __global__ void __launch_bounds__(kBlock) k_control_bin_b(Batch b) {
   control_bin_body(d, d.ctrl_other, d.vmax_other, 0, 1, bid);
 }
 
-// (2) Exclusive scan of the cell counts into cell_start, one pass with
-// decoupled look-back: block b scans kScanTile cells (8 consecutive per
-// thread), publishes its total in status word b (flag 1), adds the totals of
-// its predecessors walking back (64 at a time, one per lane of the first
-// wave) until one has published its inclusive prefix (flag 2), and publishes
-// its own.  A word packs flag << 62 | value, so one
-// 64-bit atomic carries both.  Every block publishes its total before it
-// waits, and all blocks are resident at once (at most a few dozen), so every
-// wait ends; a bounded spin latches LE_E_STATE rather than hang.  The counts
-// are cleared for the next binning pass.
+// (2) One pass over the cells in blocks of sp_cells consecutive cells.  The
+// exclusive scan of the cell counts into cell_start uses decoupled
+// look-back: block b publishes its total in status word b (flag 1), adds the
+// totals of its predecessors walking back (64 at a time, one per lane of the
+// first wave) until one has published its inclusive prefix (flag 2), and
+// publishes its own.  A word packs flag << 62 | value, so one 64-bit atomic
+// carries both.  Every block publishes its total before it waits, and blocks
+// start in grid order, so the oldest unfinished block never waits on one
+// that has not started: every wait ends; a bounded spin latches LE_E_STATE
+// rather than hang.  The counts are cleared for the next binning pass.
+//
+// With its slots known, the block moves the particles of its own cells: the
+// final slot of a particle is its cell's start plus the number of cell-mates
+// with a smaller tag, so the order is (cell, tag) whatever the arrival order.
+// Its source is the slot its tag held since the last sort (slot_of_tag);
+// its state is copied there in the other buffers.  No block reads what
+// another writes, so the sort needs no further pass.
 __device__ __forceinline__ unsigned long long scan_word(int flag, long long v) {
   return ((unsigned long long)flag << 62) | (unsigned long long)v;
 }
 
-__device__ __forceinline__ void cell_scan_body(const Dev& d, int b) {
+__device__ __forceinline__ void scan_permute_body(const Dev& d, int b) {
   if (rebuild_off(d)) return;
-  __shared__ int wsum[kScanBlock / 64];
+  __shared__ int lpre[kBlock + 1];  // exclusive prefix of the block's counts, total last
+  __shared__ int wsum[kBlock / 64];
   __shared__ long long base_sh;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int c0 = b * kScanTile + 8 * threadIdx.x;
-  int v[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) v[u] = (c0 + u < d.ncell) ? d.cell_count[c0 + u] : 0;
-  int tot = 0;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) tot += v[u];
-  int incl = tot;
+  const int c0 = b * d.sp_cells;
+  const int ncb = min(d.sp_cells, d.ncell - c0);  // cells of this block (>= 1)
+  const int v = (int)threadIdx.x < ncb ? d.cell_count[c0 + threadIdx.x] : 0;
+  int incl = v;
   for (int o = 1; o < 64; o <<= 1) {
     int t = __shfl_up(incl, o, 64);
     if (lane >= o) incl += t;
@@ -353,10 +356,12 @@ __device__ __forceinline__ void cell_scan_body(const Dev& d, int b) {
   if (lane == 63) wsum[wid] = incl;
   __syncthreads();
   int woff = 0, agg = 0;
-  for (int w = 0; w < kScanBlock / 64; ++w) {
+  for (int w = 0; w < kBlock / 64; ++w) {
     if (w < wid) woff += wsum[w];
     agg += wsum[w];
   }
+  if ((int)threadIdx.x < ncb) lpre[threadIdx.x] = woff + incl - v;
+  if (threadIdx.x == 0) lpre[ncb] = agg;
   if (wid == 0) {
     // look back with the whole first wave: lane l reads the word of block
     // p - l, so one round covers 64 predecessors; the prefix is the sum of
@@ -381,6 +386,7 @@ __device__ __forceinline__ void cell_scan_body(const Dev& d, int b) {
       if (zero & need) {  // a predecessor in reach has not published yet
         if (++spins > (1ll << 22)) {
           if (lane == 0) latch(d.flags, LE_E_STATE);
+          prefix = -1;  // no prefix: the block moves nothing
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -393,69 +399,61 @@ __device__ __forceinline__ void cell_scan_body(const Dev& d, int b) {
       p -= 64;
     }
     if (lane == 0) {
-      if (b > 0)
+      if (b > 0 && prefix >= 0)
         __hip_atomic_store(&st[b], scan_word(2, prefix + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       base_sh = prefix;
     }
   }
   __syncthreads();
-  int run = (int)base_sh + woff + incl - tot;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    if (c0 + u < d.ncell) {
-      d.cell_start[c0 + u] = run;
-      d.cell_count[c0 + u] = 0;
-    }
-    run += v[u];
+  if (base_sh < 0) return;
+  const int base = (int)base_sh;
+  if ((int)threadIdx.x < ncb) {
+    d.cell_start[c0 + threadIdx.x] = base + lpre[threadIdx.x];
+    d.cell_count[c0 + threadIdx.x] = 0;
   }
-  if (b == 0 && threadIdx.x == 0) d.cell_start[d.ncell] = d.n;
+  if (c0 + ncb == d.ncell && threadIdx.x == 0) d.cell_start[d.ncell] = base + agg;  // = n
+
+  // the block's particles, one per thread and round: k-th cell of the block
+  // with lpre[k] <= f < lpre[k + 1], arrival rank r = f - lpre[k]
+  const Ctrl* c = d.ctrl;
+  const int np = d.np;
+  const int pd = c->pos_cur, ad = c->aux_cur;  // destination buffers
+  const int ps = 1 - pd, as = 1 - ad;          // binned (source) buffers
+  for (int f = threadIdx.x; f < agg; f += kBlock) {
+    int lo = 0, hi = ncb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lpre[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    const int r = f - lpre[lo];
+    const int cnt = min(lpre[lo + 1] - lpre[lo], d.bcap);
+    if (r >= cnt) continue;  // beyond the bucket (LE_E_CAPACITY latched by the binning)
+    const int32_t* B = d.bucket + (size_t)(c0 + lo) * d.bcap;  // the cell's tags
+    const int t = B[r];
+    int rank = 0;
+    for (int q = 0; q < cnt; ++q) rank += (B[q] < t) ? 1 : 0;
+    const int ns = base + lpre[lo] + rank;
+    const int i = d.slot_of_tag[t];
+    if ((unsigned)ns >= (unsigned)d.n || (unsigned)i >= (unsigned)d.n) continue;  // (only after a latched error)
+    reinterpret_cast<double4*>(d.pos[pd])[ns] = reinterpret_cast<const double4*>(d.pos[ps])[i];
+    for (int a = 0; a < 3; ++a) {
+      d.vel[ad][a * np + ns] = d.vel[as][a * np + i];
+      d.frc[ad][a * np + ns] = d.frc[as][a * np + i];
+    }
+    d.tag[ad][ns] = t;
+    d.slot_of_tag[t] = ns;
+  }
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_cell_scan(Dev d) { cell_scan_body(d, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_scan_permute(Dev d) { scan_permute_body(d, blockIdx.x); }
 
 // Batched form: the blocks of one simulation are consecutive in the grid, so
 // every block's predecessors were dispatched before it (the look-back waits
 // only on them).
-__global__ void __launch_bounds__(kScanBlock) k_cell_scan_b(Batch b) {
+__global__ void __launch_bounds__(kBlock) k_scan_permute_b(Batch b) {
   int sm, bid;
   locate(b, blockIdx.x, sm, bid);
-  cell_scan_body(stage_dev(b.dev[sm]), bid);
-}
-
-// (3) Final slot = cell start + number of cell-mates with a smaller tag, so
-// the order is (cell, tag) whatever the arrival order; copy the particle's
-// state to the other buffers at that slot.
-__device__ __forceinline__ void permute_body(const Dev& d, int bid) {
-  if (rebuild_off(d)) return;
-  const Ctrl* c = d.ctrl;
-  const int i = bid * kBlock + threadIdx.x;
-  if (i >= d.n) return;
-  const int np = d.np;
-  const int pd = c->pos_cur, ad = c->aux_cur;  // destination buffers
-  const int ps = 1 - pd, as = 1 - ad;          // binned (source) buffers
-  const int32_t* tag = d.tag[as];
-  const int cell = d.cell_of[i];
-  const int s0 = d.cell_start[cell], cnt = min(d.cell_start[cell + 1] - s0, d.bcap);
-  const int t = tag[i];
-  const int32_t* B = d.bucket + (size_t)cell * d.bcap;
-  int r = 0;
-  for (int q = 0; q < cnt; ++q) r += (B[q] < t) ? 1 : 0;  // the bucket holds the cell's tags
-  const int ns = s0 + r;
-  reinterpret_cast<double4*>(d.pos[pd])[ns] = reinterpret_cast<const double4*>(d.pos[ps])[i];
-  for (int a = 0; a < 3; ++a) {
-    d.vel[ad][a * np + ns] = d.vel[as][a * np + i];
-    d.frc[ad][a * np + ns] = d.frc[as][a * np + i];
-  }
-  d.tag[ad][ns] = t;
-  d.slot_of_tag[t] = ns;
-}
-
-__global__ void __launch_bounds__(kBlock) k_permute(Dev d) { permute_body(d, blockIdx.x); }
-
-__global__ void __launch_bounds__(kBlock) k_permute_b(Batch b) {
-  int sm, bid;
-  locate(b, blockIdx.x, sm, bid);
-  permute_body(stage_dev(b.dev[sm]), bid);
+  scan_permute_body(stage_dev(b.dev[sm]), bid);
 }
 
 // Neighbour lists of radius r_list through the Lees-Edwards cell stencil.
@@ -1922,8 +1920,7 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
   dn.vmax = next_vmax;
   hipLaunchKernelGGL(k_control_bin, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, next, next_vmax,
                      force ? 1 : 0, control ? 1 : 0);
-  hipLaunchKernelGGL(k_cell_scan, dim3((d.ncell + kScanTile - 1) / kScanTile), dim3(kScanBlock), 0, s, dn);
-  hipLaunchKernelGGL(k_permute, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, dn);
+  hipLaunchKernelGGL(k_scan_permute, dim3(d.sp_blocks), dim3(kBlock), 0, s, dn);
   // the LDS halo of the search: full size, or smaller (more blocks per CU)
   // for sparse systems whose lists hold global slots
   if (dn.staged) hipLaunchKernelGGL((k_neighbors<kHalo, false>), dim3(d.ntiles), dim3(2 * kTile), 0, s, dn);
@@ -2066,11 +2063,10 @@ hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& par_nxt,
-                            const Batch& tile_nxt, const Dev& cfg, hipStream_t s) {
+hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& tile_nxt,
+                            const Dev& cfg, hipStream_t s) {
   hipLaunchKernelGGL(k_control_bin_b, grid_of(par_cur), dim3(kBlock), 0, s, par_cur);
-  hipLaunchKernelGGL(k_cell_scan_b, grid_of(scan_nxt), dim3(kScanBlock), 0, s, scan_nxt);
-  hipLaunchKernelGGL(k_permute_b, grid_of(par_nxt), dim3(kBlock), 0, s, par_nxt);
+  hipLaunchKernelGGL(k_scan_permute_b, grid_of(scan_nxt), dim3(kBlock), 0, s, scan_nxt);
   if (cfg.staged) hipLaunchKernelGGL((k_neighbors_b<kHalo, false>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
   else if (cfg.small_halo)
     hipLaunchKernelGGL((k_neighbors_b<kHaloSearch, true>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
