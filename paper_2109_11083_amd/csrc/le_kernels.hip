@@ -593,6 +593,8 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
     tg.row_first = ca / d.nx;
     tg.nrows = cb / d.nx - ca / d.nx + 1;
     tg.staged_ok = tg.nrows <= kMaxRows ? 1 : 0;
+    pc.nseg = 0;  // (no piece staged unless the first fits)
+    pc.ntot = 0;
   }
   __syncthreads();
   // ---- pieces: one thread per (covered row, dz, dy)
@@ -630,68 +632,61 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   }
   __syncthreads();
   // ---- LDS offsets in a fixed order (prefix sum over the pieces); pieces that
-  // do not fit stay global
+  // do not fit stay global.  One piece per thread of the first kWaves waves.
   {
-    // (the first kTile threads, two rounds; the others only meet the barriers)
+    static_assert(kMaxRows * 9 * kPieces <= kTile, "one piece per thread of the first kTile");
     __shared__ int wsum[kWaves];
-    const int npieces = ncombo * kPieces;  // <= kMaxRows * 9 * kPieces <= 2 * kTile
-    const bool pt = threadIdx.x < kTile;
-    int cnt[2], incl[2];
-    int tot_prev = 0;
-    for (int rd = 0; rd < 2; ++rd) {
-      int e = rd * kTile + (int)threadIdx.x;
-      int t = e / kPieces, q = e % kPieces;
-      cnt[rd] = (pt && e < npieces && q < pc.npc[t]) ? pc.count[t][q] : 0;
-      // block inclusive scan of cnt[rd] over the first kTile threads
-      int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      int val = cnt[rd];
-      for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(val, o, 64);
-        if (lane >= o) val += u;
-      }
-      if (lane == 63 && wv < kWaves) wsum[wv] = val;
-      __syncthreads();
-      int woff = 0, wtot = 0;
-      for (int w2 = 0; w2 < kWaves; ++w2) { if (w2 < wv) woff += wsum[w2]; wtot += wsum[w2]; }
-      incl[rd] = tot_prev + woff + val;
-      tot_prev += wtot;
-      __syncthreads();
+    const int npieces = ncombo * kPieces;
+    const int e = (int)threadIdx.x;
+    const bool pe = e < npieces;
+    const int t = pe ? e / kPieces : 0, q = e % kPieces;
+    const bool real = pe && q < pc.npc[t];
+    const int cnt = real ? pc.count[t][q] : 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
     }
+    if (lane == 63 && wv < kWaves) wsum[wv] = incl;
+    __syncthreads();
+    for (int w2 = 0; w2 < kWaves; ++w2)
+      if (w2 < wv) incl += wsum[w2];
     // a piece is staged iff it ends within the halo; the staged set is a
     // prefix of the pieces (the running offsets only grow).  The staging
     // table is that prefix, one entry per piece in order (empty ones too:
-    // the search below skips them), written by the piece's own thread.
-    if (threadIdx.x == 0) { pc.nseg = 0; pc.ntot = 0; }
-    __syncthreads();
-    for (int rd = 0; rd < 2; ++rd) {
-      int e = rd * kTile + (int)threadIdx.x;
-      if (pt && e < npieces) {
-        int t = e / kPieces, q = e % kPieces;
-        bool real = q < pc.npc[t];
-        int start_off = incl[rd] - cnt[rd];
-        const bool fits = incl[rd] <= HALO;
-        pc.off[t][q] = (real && fits) ? start_off : -1;
-        sr.st.off[e] = start_off;
-        sr.st.start[e] = real ? pc.start[t][q] : 0;
-        sr.st.code[e] = real ? pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1) : 0;
-        if (fits) {
-          atomicMax(&pc.nseg, e + 1);
-          atomicMax(&pc.ntot, incl[rd]);
-        }
+    // the search below skips them), written by the piece's own thread; the
+    // last piece that fits records the prefix's length and size.
+    if (pe) {
+      const int start_off = incl - cnt;
+      const bool fits = incl <= HALO;
+      pc.off[t][q] = (real && fits) ? start_off : -1;
+      sr.st.off[e] = start_off;
+      sr.st.start[e] = real ? pc.start[t][q] : 0;
+      sr.st.code[e] = real ? pack_img(pc.sx0[t] + q, (pc.code[t] & 3) - 1, (pc.code[t] >> 2) - 1) : 0;
+      bool next_fits = false;
+      if (e + 1 < npieces) {
+        const int t1 = (e + 1) / kPieces, q1 = (e + 1) % kPieces;
+        next_fits = incl + (q1 < pc.npc[t1] ? pc.count[t1][q1] : 0) <= HALO;
+      }
+      if (fits && !next_fits) {
+        pc.nseg = e + 1;
+        pc.ntot = incl;
       }
     }
     __syncthreads();
     if (threadIdx.x == 0) d.tile_nstage[tile] = pc.ntot;
   }
-  __syncthreads();
-  // ---- stage positions and record their slots (flat, four loads in flight)
+  // ---- stage positions and record their slots (flat, kStageLoads loads in
+  // flight per thread: the search halo in one round)
   const double4 org = P[s0];
   {
     const int tot = pc.ntot, nseg = pc.nseg;
-    for (int h0 = threadIdx.x; h0 < tot; h0 += 4 * blockDim.x) {
-      int slot[4], code[4];
+    constexpr int kStageLoads = 6;
+    for (int h0 = threadIdx.x; h0 < tot; h0 += kStageLoads * blockDim.x) {
+      int slot[kStageLoads], code[kStageLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kStageLoads; ++u) {
         int h = h0 + u * blockDim.x;
         slot[u] = n;
         code[u] = 0;
@@ -705,11 +700,11 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
           code[u] = sr.st.code[lo];
         }
       }
-      double4 pj[4];
+      double4 pj[kStageLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pj[u] = P[slot[u]];
+      for (int u = 0; u < kStageLoads; ++u) pj[u] = P[slot[u]];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kStageLoads; ++u) {
         const int h = h0 + u * blockDim.x;
         // written unconditionally (past the halo: a spare entry) so that the
         // loads above are not sunk into the condition one by one
