@@ -478,11 +478,6 @@ __global__ void __launch_bounds__(kBlock) k_scan_permute_b(Batch b) {
 // others store the partner's slot and image code in one 32-bit word.  Lists
 // are padded with sentinels (LDS index kHalo, slot n) to whole batches.
 
-struct TileGeom {
-  int row_first, nrows, staged_ok;
-  int c_first, c_last;
-};
-
 // Element k of particle i in the blocked list layouts (see Dev).
 __device__ __forceinline__ size_t idx8(int k, int i, int np) {
   return ((size_t)(k >> 3) * np + i) * 8 + (k & 7);
@@ -523,7 +518,6 @@ struct Pieces {
   int npc[kMaxRows * 9];
   int code[kMaxRows * 9];          // image code (sy, sz) of the row; sx added per piece
   int nseg, ntot;
-  TileGeom tg;
 };
 
 // Exact list test of one pair: the plain-definition displacement between
@@ -566,11 +560,8 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   // halo tables in global memory then)
   __shared__ __align__(16) uint32_t gslot[GL ? 2 * kTile : 1][kOtherBatch];
   __shared__ uint32_t hent[GL ? HALO + 8 : 1];
-  __shared__ int skip;
   Ctrl* c = d.ctrl;
-  if (threadIdx.x == 0) skip = rebuild_off(d) ? 1 : 0;
-  __syncthreads();
-  if (skip) return;
+  if (rebuild_off(d)) return;  // (the same two words for every wave)
   const int np = d.np, np2 = d.np2, K = d.K, n = d.n;
   const int s0 = tile * kTile;
   const int half = (int)(threadIdx.x / kTile);
@@ -582,30 +573,25 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   const double4* P = reinterpret_cast<const double4*>(d.pos[pn]);
   const double Delta = c->Delta;
   const double rmarg = d.rlist * (1.0 + 1e-12) + 1e-12 * (d.Lx + d.Ly + d.Lz);
-  TileGeom& tg = pc.tg;
 
-  // ---- tile geometry
+  // ---- tile geometry (every thread: the cells of the tile's first and last
+  // particle, read through the scalar cache)
+  const int c_first = cell_of_pos(d, P[s0]), c_last = cell_of_pos(d, P[min(s0 + kTile, n) - 1]);
+  const int row_first = c_first / d.nx, nrows = c_last / d.nx - row_first + 1;
+  const bool staged_ok = nrows <= kMaxRows;
   if (threadIdx.x == 0) {
-    int last = min(s0 + kTile, n) - 1;
-    int ca = cell_of_pos(d, P[s0]), cb = cell_of_pos(d, P[last]);
-    tg.c_first = ca;
-    tg.c_last = cb;
-    tg.row_first = ca / d.nx;
-    tg.nrows = cb / d.nx - ca / d.nx + 1;
-    tg.staged_ok = tg.nrows <= kMaxRows ? 1 : 0;
     pc.nseg = 0;  // (no piece staged unless the first fits)
     pc.ntot = 0;
   }
-  __syncthreads();
   // ---- pieces: one thread per (covered row, dz, dy)
-  const int ncombo = tg.staged_ok ? tg.nrows * 9 : 0;
+  const int ncombo = staged_ok ? nrows * 9 : 0;
   for (int t = threadIdx.x; t < ncombo; t += blockDim.x) {
     int r = t / 9, rem = t % 9;
     int dzc = rem / 3 - 1, dyc = rem % 3 - 1;
-    int row = tg.row_first + r;
+    int row = row_first + r;
     int iy = row % d.ny, iz = row / d.ny;
-    int xa = (r == 0) ? tg.c_first % d.nx : 0;
-    int xb = (r == tg.nrows - 1) ? tg.c_last % d.nx : d.nx - 1;
+    int xa = (r == 0) ? c_first % d.nx : 0;
+    int xb = (r == nrows - 1) ? c_last % d.nx : d.nx - 1;
     int jz = iz + dzc, sz = jz < 0 ? -1 : (jz >= d.nz ? 1 : 0);
     jz -= sz * d.nz;
     int jy = iy + dyc, sy = jy < 0 ? -1 : (jy >= d.ny ? 1 : 0);
@@ -737,8 +723,8 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   const int ix = cell_index(pi.x, d.inv_lx, d.nx);
   const int iy = cell_index(pi.y, d.inv_ly, d.ny);
   const int iz = cell_index(pi.z, d.inv_lz, d.nz);
-  const int rt = (iz * d.ny + iy) - tg.row_first;  // tile row of the particle
-  const bool row_staged = valid && tg.staged_ok && rt >= 0 && rt < tg.nrows;
+  const int rt = (iz * d.ny + iy) - row_first;  // tile row of the particle
+  const bool row_staged = valid && staged_ok && rt >= 0 && rt < nrows;
   int self_h = -1;  // LDS position of the particle itself (plain image)
   if (row_staged) {
     const int t = rt * 9 + 4;  // dz = dy = 0
