@@ -1537,11 +1537,6 @@ __device__ __forceinline__ void force_body(const Dev& d, const int lb, double* _
   }
 }
 
-// The float64 DPD form is held to 3 waves per SIMD (at most 168 VGPRs): it
-// is latency-bound, and 2 waves made it 1.45x slower.
-template <int MODE, bool MIXED, bool STAGED>
-constexpr int force_waves() { return MODE == kDpdForce && !MIXED && !STAGED ? 3 : 1; }
-
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
 __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile)
     k_force(Dev d, double* __restrict__ f_out, double* __restrict__ sample_out) {
