@@ -46,11 +46,6 @@ STEP_FLOPS = 40.0             # thermostat + velocity Verlet per particle
 BYTES_FUSED = 100.0           # fused step, per particle: read x, u, tag; write x, u
 TIMING_FORCE = 0x1 | (8 << 8)  # event-time every 8th plain-step force launch (phase 0)
 
-
-def timing_force(steps):
-    """Event-timing mask of the timed run: every plain-step force launch of a short
-    run (the start/stop events ride on the dispatch itself), every 8th of a long one."""
-    return 0x1 | ((1 if steps < 512 else 8) << 8)
 ETA_STEPS = 25000             # fixed length of each viscosity run (independent of --steps)
 ETA_WARMUP = 2000
 ETA_WINDOW = 0.2              # last 20% of the samples (Fig. profile caption)
@@ -567,7 +562,7 @@ def main():
     x, u, p = workload(args.workload, sr, args.precision, skin=skin, n=args.n, thermostat=th)
     log(f"bench: {args.workload} n={p.n} shear_rate={sr} {args.precision} steps={args.steps} "
         f"warmup={args.warmup} skin={skin}")
-    r = run_gpu(x, u, p, args.steps, args.warmup, timing=0 if args.no_timing else timing_force(args.steps))
+    r = run_gpu(x, u, p, args.steps, args.warmup, timing=0 if args.no_timing else TIMING_FORCE)
     log(f"bench: {r['value']:.4e} particle-steps/s, {r['ms_per_step']:.4f} ms/step, "
         f"rebuilds={r['rebuilds']}, force={r['phases']['force']}")
     roofline = roofline_of(r, args.workload, args.precision, skin[0], dpd=dpd)
