@@ -142,6 +142,40 @@ def test_cells_and_pairs_wca_small_cells():
         _check_cells_pairs(w.x, w.u, p, step0)
 
 
+def test_sort_at_extreme_cell_occupancies():
+    """The scan-and-permute pass at its two extremes: about 555 particles per
+    cell (one cell per block of the pass) and one particle per 20 cells (256
+    cells per block, a ragged last block).  The (cell, tag) order and the
+    wrapped state must equal the oracle's bit for bit."""
+    rng = np.random.default_rng(11)
+    n = 15000
+    box = (3.7, 3.7, 3.7)
+    x = np.stack([rng.uniform(0.0, box[a], n) for a in range(3)])
+    u = rng.normal(size=(3, n))
+    p = Params(n=n, box=box, shear_rate=0.4, rc=1.0, skin=0.2, eps=0.0, cells=(3, 3, 3), seed=5,
+               max_neighbors=6000)
+    _log(f"dense sort n={n} cells=27")
+    sim = Sim(p, x, u, step0=9)
+    out = sim.build_cells(want_pairs=False)
+    _log(f"dense sort: largest list {sim.stats()['max_neighbors']}")
+    op = _oracle_params(p)
+    Delta = O.offset(9, p.dt, p.shear_rate, p.box[0], p.box[1])
+    xw, uw = O.le_wrap(x, u, Delta, op)
+    cell_ref, order_ref = O.cells(xw, (3, 3, 3), p.box)
+    assert np.array_equal(out["cell_of"], cell_ref)
+    assert np.array_equal(out["order"], order_ref)
+    xs, us, _, _ = sim.state()
+    assert np.array_equal(xs, xw) and np.array_equal(us, uw)
+    sim.close()
+    # sparse: 500 particles over 21^3 cells
+    m = 500
+    sbox = (30.0, 30.0, 30.0)
+    xs0 = np.stack([rng.uniform(0.0, sbox[a], m) for a in range(3)])
+    us0 = rng.normal(size=(3, m))
+    ps = Params(n=m, box=sbox, shear_rate=0.2, rc=2 ** (1 / 6), pair="wca", skin=0.3, seed=6)
+    _check_cells_pairs(xs0, us0, ps, 31)
+
+
 # ------------------------------------------------------------------ forces, stress
 def _forces_case(w_x, w_u, p: Params, step0, tol_f, tol_w, method=0):
     sim = Sim(p, w_x, w_u, step0=step0)
