@@ -154,7 +154,7 @@ size_t carve(const le_params* p, const Geometry& g, char* base, Dev* d, le_sim* 
   }
   t.vt = (p->thermostat == LE_THERMO_DPD) ? (double*)take(4 * np * sizeof(double)) : nullptr;
   t.slot_of_tag = (int32_t*)take(np * sizeof(int32_t));
-  t.bucket = (int32_t*)take(ncell * (size_t)g.bcap * sizeof(int32_t));
+  t.bucket = (int2*)take(ncell * (size_t)g.bcap * sizeof(int2));
   t.cell_count = (int32_t*)take(ncell * sizeof(int32_t));
   t.cell_start = (int32_t*)take((ncell + 1) * sizeof(int32_t));
   t.nl16 = (uint16_t*)take((size_t)g.K * 2 * np * sizeof(uint16_t));

@@ -104,7 +104,8 @@ struct Dev {
   int32_t* tag[2];                 // slot -> tag
   int32_t* slot_of_tag;            // tag -> slot
   int32_t bcap;                    // bucket capacity per cell
-  int32_t* bucket;                 // [ncell][bcap] tags binned into each cell (arrival order)
+  int2* bucket;                    // [ncell][bcap] (tag, slot) of the particles binned into each
+                                   // cell, in arrival order
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
   // Neighbour lists: two sub-lists per particle (v = h * np + i, h = 0, 1,

@@ -135,7 +135,6 @@ __global__ void k_load_state(Dev d, const double* __restrict__ x0, const double*
       d.frc[0][a * np + i] = f0 ? f0[a * n + i] : 0.0;
     }
     d.tag[0][i] = i;
-    d.slot_of_tag[i] = i;
   }
   if (i == 0) {
     // far-away sentinel at slot n pads neighbour batches: r^2 ~ 1e200 never passes a cutoff
@@ -216,7 +215,7 @@ __device__ __forceinline__ bool rebuild_off(const Dev& d) {
 // (1) Reads control copy d.ctrl and writes the next one (block 0).  With
 // `control` the step is advanced first (after a drift).  On a rebuild:
 // boundary crossing (Lees-Edwards shift and velocity jump) + periodic wrap of
-// x and z in place, then each particle's tag goes into its cell's bucket at
+// x and z in place, then each particle's tag and slot go into its cell's bucket at
 // its arrival rank.  Runs of equal cells within a wave take one atomic per run.
 __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict__ next,
                                                  unsigned long long* __restrict__ next_vmax, int force,
@@ -298,7 +297,7 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
   base = __shfl(base, run0, 64);
   if (cell >= 0) {
     const int r = base + (lane - run0);
-    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = d.tag[sc.aux_cur][i];
+    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = make_int2(d.tag[sc.aux_cur][i], i);
     else latch(d.flags, LE_E_CAPACITY);
   }
 }
@@ -332,8 +331,8 @@ __global__ void __launch_bounds__(kBlock) k_control_bin_b(Batch b) {
 // With its slots known, the block moves the particles of its own cells: the
 // final slot of a particle is its cell's start plus the number of cell-mates
 // with a smaller tag, so the order is (cell, tag) whatever the arrival order.
-// Its source is the slot its tag held since the last sort (slot_of_tag);
-// its state is copied there in the other buffers.  No block reads what
+// The bucket entry carries the particle's binned slot; its state is copied
+// from there to the final slot in the other buffers.  No block reads what
 // another writes, so the sort needs no further pass.
 __device__ __forceinline__ unsigned long long scan_word(int flag, long long v) {
   return ((unsigned long long)flag << 62) | (unsigned long long)v;
@@ -413,13 +412,19 @@ __device__ __forceinline__ void scan_permute_body(const Dev& d, int b) {
   }
   if (c0 + ncb == d.ncell && threadIdx.x == 0) d.cell_start[d.ncell] = base + agg;  // = n
 
-  // the block's particles, one per thread and round: k-th cell of the block
-  // with lpre[k] <= f < lpre[k + 1], arrival rank r = f - lpre[k]
+  // the block's particles, two per thread and round (their loads overlap):
+  // k-th cell of the block with lpre[k] <= f < lpre[k + 1], arrival rank
+  // r = f - lpre[k]; the bucket entry holds the tag and the binned slot
   const Ctrl* c = d.ctrl;
   const int np = d.np;
   const int pd = c->pos_cur, ad = c->aux_cur;  // destination buffers
   const int ps = 1 - pd, as = 1 - ad;          // binned (source) buffers
-  for (int f = threadIdx.x; f < agg; f += kBlock) {
+  // the final slot (-1: none), binned slot and tag of the block's f-th particle
+  auto locate_f = [&](int f, int& ns, int& src, int& tg) {
+    ns = -1;
+    src = 0;
+    tg = 0;
+    if (f >= agg) return;
     int lo = 0, hi = ncb - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -427,21 +432,42 @@ __device__ __forceinline__ void scan_permute_body(const Dev& d, int b) {
     }
     const int r = f - lpre[lo];
     const int cnt = min(lpre[lo + 1] - lpre[lo], d.bcap);
-    if (r >= cnt) continue;  // beyond the bucket (LE_E_CAPACITY latched by the binning)
-    const int32_t* B = d.bucket + (size_t)(c0 + lo) * d.bcap;  // the cell's tags
-    const int t = B[r];
+    if (r >= cnt) return;  // beyond the bucket (LE_E_CAPACITY latched by the binning)
+    const int2* B = d.bucket + (size_t)(c0 + lo) * d.bcap;
+    const int2 e = B[r];
     int rank = 0;
-    for (int q = 0; q < cnt; ++q) rank += (B[q] < t) ? 1 : 0;
-    const int ns = base + lpre[lo] + rank;
-    const int i = d.slot_of_tag[t];
-    if ((unsigned)ns >= (unsigned)d.n || (unsigned)i >= (unsigned)d.n) continue;  // (only after a latched error)
-    reinterpret_cast<double4*>(d.pos[pd])[ns] = reinterpret_cast<const double4*>(d.pos[ps])[i];
-    for (int a = 0; a < 3; ++a) {
-      d.vel[ad][a * np + ns] = d.vel[as][a * np + i];
-      d.frc[ad][a * np + ns] = d.frc[as][a * np + i];
+    for (int q = 0; q < cnt; ++q) rank += (B[q].x < e.x) ? 1 : 0;
+    const int s = base + lpre[lo] + rank;
+    if ((unsigned)s < (unsigned)d.n && (unsigned)e.y < (unsigned)d.n) {  // (else a latched error)
+      ns = s;
+      src = e.y;
+      tg = e.x;
     }
-    d.tag[ad][ns] = t;
-    d.slot_of_tag[t] = ns;
+  };
+  struct St { double4 p; double v0, v1, v2, f0, f1, f2; };
+  auto load = [&](int i) -> St {
+    const double* V = d.vel[as];
+    const double* F = d.frc[as];
+    return St{reinterpret_cast<const double4*>(d.pos[ps])[i], V[i], V[np + i], V[2 * np + i],
+              F[i], F[np + i], F[2 * np + i]};
+  };
+  auto store = [&](int ns, int tg, const St& v) {
+    if (ns < 0) return;
+    reinterpret_cast<double4*>(d.pos[pd])[ns] = v.p;
+    double* V = d.vel[ad];
+    double* F = d.frc[ad];
+    V[ns] = v.v0; V[np + ns] = v.v1; V[2 * np + ns] = v.v2;
+    F[ns] = v.f0; F[np + ns] = v.f1; F[2 * np + ns] = v.f2;
+    d.tag[ad][ns] = tg;
+    d.slot_of_tag[tg] = ns;
+  };
+  for (int f0 = threadIdx.x; f0 < agg; f0 += 2 * kBlock) {
+    int ns0, src0, tg0, ns1, src1, tg1;
+    locate_f(f0, ns0, src0, tg0);
+    locate_f(f0 + kBlock, ns1, src1, tg1);
+    const St a0 = load(src0), a1 = load(src1);  // (slot 0 for an empty lane: in bounds, not stored)
+    store(ns0, tg0, a0);
+    store(ns1, tg1, a1);
   }
 }
 
