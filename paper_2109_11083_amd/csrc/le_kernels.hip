@@ -32,6 +32,18 @@ __device__ __forceinline__ int xcd_map(int b, int nblocks) {
 }
 __device__ __forceinline__ int xcd_block(int nblocks) { return xcd_map((int)blockIdx.x, nblocks); }
 
+// The other way round: runs of C consecutive blocks are dealt round-robin to
+// the XCDs, so that any stretch of the grid (the tiles of the members of a
+// batch that rebuild at this step) is spread over all of them.
+template <int C>
+__device__ __forceinline__ int xcd_spread(int b, int nblocks) {
+  const int X = 8, G = X * C;
+  const int full = nblocks / G * G;
+  if (b >= full) return b;
+  const int x = b % X, k = b / X;
+  return ((k / C) * X + x) * C + k % C;
+}
+
 // Simulation and local block of global block g of a batched launch: the last
 // simulation whose first block is at or before g (simulations without blocks
 // are skipped).  Uniform across the block.
@@ -946,12 +958,15 @@ __global__ void __launch_bounds__(2 * kTile) k_neighbors(Dev d) {
   neighbors_body<HALO, GL>(d, xcd_block(d.ntiles));
 }
 
-// Batched form: the XCD remap runs over the whole grid (each XCD takes a
-// contiguous range of tiles across the simulations), then the tile is located.
+constexpr int kSpreadRun = 4;  // consecutive tiles per run of the batched list search
+
+// Batched form: only the members that rebuild at this step have work, so the
+// blocks are spread over the XCDs in short runs (xcd_spread) rather than in
+// one contiguous range per XCD; then the tile is located.
 template <int HALO, bool GL>
 __global__ void __launch_bounds__(2 * kTile) k_neighbors_b(Batch b) {
   int sm, tile;
-  locate(b, xcd_map((int)blockIdx.x, (int)gridDim.x), sm, tile);
+  locate(b, xcd_spread<kSpreadRun>((int)blockIdx.x, (int)gridDim.x), sm, tile);
   neighbors_body<HALO, GL>(stage_dev(b.dev[sm]), tile);
 }
 
