@@ -1096,7 +1096,7 @@ __device__ __forceinline__ double lj_masked(double r2, double rc2, double sig2, 
     inv = fma(inv, e, inv);
     double s2 = sig2 * inv;
     double s6 = s2 * s2 * s2;
-    double f = eps24 * s6 * fma(2.0, s6, -1.0) * inv;
+    double f = s6 * fma(2.0 * eps24, s6, -eps24) * inv;  // 24 eps s6 (2 s6 - 1) / r^2
     if (CAP) {
       const double lim = cap / sqrt(r2);
       f = fmin(fmax(f, -lim), lim);
