@@ -380,7 +380,7 @@ namespace {
 struct BatchGroup {
   Dev cfg;                     // host descriptor of the first member (kernel configuration)
   std::vector<le_sim*> sims;
-  Batch par[2], scan[2], tile[2], one[2];  // [v]: v = 0 descriptors of the copies current at the call
+  Batch par[2], bin[2], scan[2], tile[2], one[2];  // [v]: v = 0 descriptors of the copies current at the call
 };
 
 bool same_config(const Dev& a, const Dev& b) {
@@ -391,24 +391,27 @@ bool same_config(const Dev& a, const Dev& b) {
 
 void fill_group(BatchGroup& g) {
   for (int v = 0; v < 2; ++v) {
-    Batch* bs[4] = {&g.par[v], &g.scan[v], &g.tile[v], &g.one[v]};
+    Batch* bs[5] = {&g.par[v], &g.bin[v], &g.scan[v], &g.tile[v], &g.one[v]};
     for (Batch* b : bs) {
       memset(b, 0, sizeof(Batch));
       b->nsims = (int32_t)g.sims.size();
     }
-    int32_t op = 0, os = 0, ot = 0;
+    int32_t op = 0, ob = 0, os = 0, ot = 0;
     for (size_t k = 0; k < g.sims.size(); ++k) {
       le_sim* s = g.sims[k];
       const int cur = s->d.ctrl == s->ctrl_base ? 0 : 1;
       const Dev* dv = s->dev_dev + (cur ^ v);
-      g.par[v].start[k] = op; g.scan[v].start[k] = os; g.tile[v].start[k] = ot; g.one[v].start[k] = (int32_t)k;
-      g.par[v].dev[k] = g.scan[v].dev[k] = g.tile[v].dev[k] = g.one[v].dev[k] = dv;
+      g.par[v].start[k] = op; g.bin[v].start[k] = ob; g.scan[v].start[k] = os; g.tile[v].start[k] = ot;
+      g.one[v].start[k] = (int32_t)k;
+      g.par[v].dev[k] = g.bin[v].dev[k] = g.scan[v].dev[k] = g.tile[v].dev[k] = g.one[v].dev[k] = dv;
       op += (s->d.n + kBlock - 1) / kBlock;
+      ob += (s->d.n + kBinBlock - 1) / kBinBlock;
       os += s->d.sp_blocks;
       ot += s->d.ntiles;
     }
     const size_t m = g.sims.size();
-    g.par[v].start[m] = op; g.scan[v].start[m] = os; g.tile[v].start[m] = ot; g.one[v].start[m] = (int32_t)m;
+    g.par[v].start[m] = op; g.bin[v].start[m] = ob; g.scan[v].start[m] = os; g.tile[v].start[m] = ot;
+    g.one[v].start[m] = (int32_t)m;
   }
 }
 
@@ -451,7 +454,7 @@ le_status step_batch(std::vector<BatchGroup>& groups, hipStream_t q, int64_t nst
   for (BatchGroup& g : groups)
     if (st == LE_OK) st = hip_check(launch_kick_drift_b(g.par[v], q));
   for (BatchGroup& g : groups)
-    if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+    if (st == LE_OK) st = hip_check(launch_rebuild_b(g.bin[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
   v ^= 1;
   int64_t ns = 0;
   for (int64_t k = 1; k <= nsteps && st == LE_OK; ++k) {
@@ -475,7 +478,7 @@ le_status step_batch(std::vector<BatchGroup>& groups, hipStream_t q, int64_t nst
     if (sample) ++ns;
     if (st == LE_OK && !last) {
       for (BatchGroup& g : groups)
-        if (st == LE_OK) st = hip_check(launch_rebuild_b(g.par[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
+        if (st == LE_OK) st = hip_check(launch_rebuild_b(g.bin[v], g.scan[v ^ 1], g.tile[v ^ 1], g.cfg, q));
       v ^= 1;
     }
   }

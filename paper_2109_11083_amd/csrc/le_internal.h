@@ -27,6 +27,7 @@ constexpr int kSlots = 64;         // words (one per 128-byte line) a block maxi
 constexpr int kLineInts = 32;      // 32-bit words per 128-byte line
 constexpr int kLineU64 = 16;       // 64-bit words per 128-byte line
 constexpr int kSortParticles = 512;  // particles per block of the scan-and-permute pass (on average)
+constexpr int kBinBlock = 2 * kBlock;  // particles per block of the binning pass (two per thread)
 
 // Mutable per-simulation scalars that live on the device so that a step
 // never needs the host: step counter, offset, rebuild bookkeeping.  Two
@@ -202,12 +203,13 @@ hipError_t launch_status_out(const Dev& d, hipStream_t s, int32_t* out);
 // Batched launchers: one launch over the blocks of every simulation of a
 // batch (all of one kernel configuration, given by `cfg`, the host copy of any
 // member's descriptor).  Batches by block kind: `par` one block per kBlock
-// particles, `scan` one per sp_cells cells, `tile` one per kTile particles,
+// particles, `bin` one per kBinBlock particles, `scan` one per sp_cells cells,
+// `tile` one per kTile particles,
 // `one` one block per simulation; `cur` and `nxt` name the descriptors of the
 // current and the other control copy.
 hipError_t launch_store_dev(const Dev& a, const Dev& b, Dev* dst, hipStream_t s);
 hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s);
-hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& tile_nxt,
+hipError_t launch_rebuild_b(const Batch& bin_cur, const Batch& scan_nxt, const Batch& tile_nxt,
                             const Dev& cfg, hipStream_t s);
 hipError_t launch_force_b(const Batch& tile_cur, const Batch& par_cur, const Dev& cfg, hipStream_t s,
                           ForceMode mode, bool sample);

@@ -263,54 +263,58 @@ __device__ __forceinline__ void control_bin_body(const Dev& d, Ctrl* __restrict_
   }
   __syncthreads();
   if (!go) return;
-  const int i = bid * kBlock + threadIdx.x;
   // the look-back words of the scan start cleared (spread over the blocks)
-  for (int k = i; k < d.sp_blocks; k += ((d.n + kBlock - 1) / kBlock) * kBlock) d.scan_status[k] = 0ull;
+  const int nbb = (d.n + kBinBlock - 1) / kBinBlock;  // blocks of this pass
+  for (int k = bid * kBlock + (int)threadIdx.x; k < d.sp_blocks; k += nbb * kBlock) d.scan_status[k] = 0ull;
   const int np = d.np;
-  int cell = -1;
-  if (i < d.n) {
-    double4* P = reinterpret_cast<double4*>(d.pos[sc.pos_cur]);
-    double* U = d.vel[sc.aux_cur];
-    double4 p = P[i];
-    double x = p.x, y = p.y, z = p.z;
-    double ux = U[i];
-    const double Delta = sc.Delta;
-    double ky = wrap1(y, d.Ly);
-    x = x - ky * Delta;
-    ux = ux - ky * d.jump_sv;  // velocity jump (lab storage only)
-    wrap1(x, d.Lx);
-    double kz = wrap1(z, d.Lz);
-    int cy, cz;
-    img_get(p.w, cy, cz);
-    p.w = img_put(cy + (int)ky, cz + (int)kz);
-    double uy = U[np + i], uz = U[2 * np + i];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
-      latch(d.flags, LE_E_NONFINITE);
-      x = 0.0; y = 0.0; z = 0.0;
+  for (int rd = 0; rd < kBinBlock / kBlock; ++rd) {
+    const int i = bid * kBinBlock + rd * kBlock + (int)threadIdx.x;
+    int cell = -1, tg = 0;
+    if (i < d.n) {
+      tg = d.tag[sc.aux_cur][i];
+      double4* P = reinterpret_cast<double4*>(d.pos[sc.pos_cur]);
+      double* U = d.vel[sc.aux_cur];
+      double4 p = P[i];
+      double x = p.x, y = p.y, z = p.z;
+      double ux = U[i];
+      const double Delta = sc.Delta;
+      double ky = wrap1(y, d.Ly);
+      x = x - ky * Delta;
+      ux = ux - ky * d.jump_sv;  // velocity jump (lab storage only)
+      wrap1(x, d.Lx);
+      double kz = wrap1(z, d.Lz);
+      int cy, cz;
+      img_get(p.w, cy, cz);
+      p.w = img_put(cy + (int)ky, cz + (int)kz);
+      double uy = U[np + i], uz = U[2 * np + i];
+      if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
+        latch(d.flags, LE_E_NONFINITE);
+        x = 0.0; y = 0.0; z = 0.0;
+      }
+      p.x = x; p.y = y; p.z = z;
+      P[i] = p;
+      U[i] = ux;
+      int ix = cell_index(x, d.inv_lx, d.nx);
+      int iy = cell_index(y, d.inv_ly, d.ny);
+      int iz = cell_index(z, d.inv_lz, d.nz);
+      cell = (iz * d.ny + iy) * d.nx + ix;
     }
-    p.x = x; p.y = y; p.z = z;
-    P[i] = p;
-    U[i] = ux;
-    int ix = cell_index(x, d.inv_lx, d.nx);
-    int iy = cell_index(y, d.inv_ly, d.ny);
-    int iz = cell_index(z, d.inv_lz, d.nz);
-    cell = (iz * d.ny + iy) * d.nx + ix;
-  }
-  // runs of equal cells among consecutive lanes share one atomic
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(cell, 1, 64);
-  const bool head = lane == 0 || prev != cell;
-  const unsigned long long heads = __ballot(head);
-  const int run0 = 63 - __clzll(heads & ((2ull << lane) - 1ull));  // lane 63: mask all ones
-  const unsigned long long after = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1ull));
-  const int run1 = after ? __ffsll((long long)after) - 1 : 64;  // first lane of the next run
-  int base = 0;
-  if (head && cell >= 0) base = atomicAdd(&d.cell_count[cell], run1 - lane);
-  base = __shfl(base, run0, 64);
-  if (cell >= 0) {
-    const int r = base + (lane - run0);
-    if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = make_int2(d.tag[sc.aux_cur][i], i);
-    else latch(d.flags, LE_E_CAPACITY);
+    // runs of equal cells among consecutive lanes share one atomic
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(cell, 1, 64);
+    const bool head = lane == 0 || prev != cell;
+    const unsigned long long heads = __ballot(head);
+    const int run0 = 63 - __clzll(heads & ((2ull << lane) - 1ull));  // lane 63: mask all ones
+    const unsigned long long after = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1ull));
+    const int run1 = after ? __ffsll((long long)after) - 1 : 64;  // first lane of the next run
+    int base = 0;
+    if (head && cell >= 0) base = atomicAdd(&d.cell_count[cell], run1 - lane);
+    base = __shfl(base, run0, 64);
+    if (cell >= 0) {
+      const int r = base + (lane - run0);
+      if (r < d.bcap) d.bucket[(size_t)cell * d.bcap + r] = make_int2(tg, i);
+      else latch(d.flags, LE_E_CAPACITY);
+    }
   }
 }
 
@@ -1946,7 +1950,7 @@ hipError_t launch_rebuild(const Dev& d, Ctrl* next, unsigned long long* next_vma
   Dev dn = d;
   dn.ctrl = next;
   dn.vmax = next_vmax;
-  hipLaunchKernelGGL(k_control_bin, dim3(blocks_for(d.n)), dim3(kBlock), 0, s, d, next, next_vmax,
+  hipLaunchKernelGGL(k_control_bin, dim3((d.n + kBinBlock - 1) / kBinBlock), dim3(kBlock), 0, s, d, next, next_vmax,
                      force ? 1 : 0, control ? 1 : 0);
   hipLaunchKernelGGL(k_scan_permute, dim3(d.sp_blocks), dim3(kBlock), 0, s, dn);
   // the LDS halo of the search: full size, or smaller (more blocks per CU)
@@ -2091,9 +2095,9 @@ hipError_t launch_kick_drift_b(const Batch& par_cur, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rebuild_b(const Batch& par_cur, const Batch& scan_nxt, const Batch& tile_nxt,
+hipError_t launch_rebuild_b(const Batch& bin_cur, const Batch& scan_nxt, const Batch& tile_nxt,
                             const Dev& cfg, hipStream_t s) {
-  hipLaunchKernelGGL(k_control_bin_b, grid_of(par_cur), dim3(kBlock), 0, s, par_cur);
+  hipLaunchKernelGGL(k_control_bin_b, grid_of(bin_cur), dim3(kBlock), 0, s, bin_cur);
   hipLaunchKernelGGL(k_scan_permute_b, grid_of(scan_nxt), dim3(kBlock), 0, s, scan_nxt);
   if (cfg.staged) hipLaunchKernelGGL((k_neighbors_b<kHalo, false>), grid_of(tile_nxt), dim3(2 * kTile), 0, s, tile_nxt);
   else if (cfg.small_halo)
