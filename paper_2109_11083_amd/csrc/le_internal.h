@@ -110,7 +110,7 @@ struct Dev {
   int32_t* cell_count;             // [ncell]
   int32_t* cell_start;             // [ncell + 1]
   // Neighbour lists: two sub-lists per particle (v = h * np + i, h = 0, 1,
-  // the two halves of each stencil range).  Entry k of sub-list v lives in a
+  // alternate batches of 8 candidates of each stencil range).  Entry k of sub-list v lives in a
   // block of consecutive entries: blocks of 8 (one 16-byte load) for nl16, of
   // 4 for nlo; block b of sub-lists v, v+1, ... is contiguous.
   //   nl16  partners staged in the tile's LDS halo (any image): LDS index,

@@ -757,9 +757,11 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
   // ---- scan: each lane walks its own stencil.  For each (dy, dz) the x-cells
   // the particle reaches in that row form one contiguous LDS range (the row's
   // x-image pieces are staged back to back, images already added), so a lane
-  // tests [a, b) with eight candidates per batch; the wave runs to its
-  // longest range.  Lanes whose row was not staged walk the cells in global
-  // memory with the exact test instead.
+  // tests [a, b) with eight candidates per batch, the particle's two threads
+  // taking alternate batches (each sub-list then holds partners from all
+  // over the row: fewer padding entries and gathers spread alike); the wave
+  // runs to its longest range.  Lanes whose row was not staged walk the cells
+  // in global memory with the exact test instead.
   const double4 pi = P[valid ? i : s0];
   const float pix = (float)(pi.x - org.x), piy = (float)(pi.y - org.y), piz = (float)(pi.z - org.z);
   const int ix = cell_index(pi.x, d.inv_lx, d.nx);
@@ -812,9 +814,8 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
       if (qa >= 0 && qb < pc.npc[t] && pc.off[t][qb] >= 0) {
         a = d.cell_start[rowbase + (klo - sxa * d.nx)] + (pc.off[t][qa] - pc.start[t][qa]);
         b = d.cell_start[rowbase + (khi - sxb * d.nx) + 1] + (pc.off[t][qb] - pc.start[t][qb]);
-        // the two threads of the particle take the two halves of the range
-        const int mid = a + (b - a + 1) / 2;
-        if (half == 0) b = mid; else a = mid;
+        // the two threads of the particle take alternate batches of the range
+        a += 8 * half;
         walk_global = false;
       }
     }
@@ -822,7 +823,7 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
     for (int o = 32; o > 0; o >>= 1) wlen = max(wlen, __shfl_xor(wlen, o, 64));
     wlen = __builtin_amdgcn_readfirstlane(wlen);
     const int sq = (c9 == 4) ? self_h : -1;
-    for (int j0 = 0; j0 < wlen; j0 += 8) {
+    for (int j0 = 0; j0 < wlen; j0 += 16) {
       const int h0 = a + j0;
       // candidates past the lane's range are read (in bounds) and masked off
       const int lim = b - h0;
