@@ -1602,6 +1602,15 @@ __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile)
 // region); LDS halo: runs of 16 tiles dealt round-robin to the XCDs, which
 // evens out members of unequal cost per tile (64-request batch 0.711 ->
 // 0.699 ms per step; the KG melts of the global layout gain nothing from it).
+// Plain DPD steps (global layout, no stress sample): held to 168 VGPRs, three
+// waves per SIMD instead of two, which the kernel reaches without spills (the
+// sampling variant would spill, so it keeps the plain bound).
+template <bool MIXED, bool BONDS>
+__global__ void __launch_bounds__(4 * kTile) __attribute__((amdgpu_waves_per_eu(3)))
+    k_force_dpd(Dev d, double* __restrict__ f_out, double* __restrict__ sample_out) {
+  (void)sample_out;
+  force_body<kDpdForce, MIXED, BONDS, false, false, false>(d, xcd_block(d.ntiles), f_out);
+}
 template <int MODE, bool MIXED, bool BONDS, bool SAMPLE, bool STAGED, bool CAP = false>
 __global__ void __launch_bounds__(STAGED ? kForceTPP * kTile : 4 * kTile) k_force_b(Batch b) {
   int sm, lb;
@@ -1988,7 +1997,15 @@ static void launch_force_s(const Dev& d, hipStream_t s, double* f_out, double* s
       return;
     }
   }
-  if (mixed) {
+  if constexpr (MODE == kDpdForce && !SAMPLE && !STAGED) {
+    if (mixed) {
+      if (bonds) launch_k(k_force_dpd<true, true>, g, b, s, e0, e1, d, f_out, so);
+      else launch_k(k_force_dpd<true, false>, g, b, s, e0, e1, d, f_out, so);
+    } else {
+      if (bonds) launch_k(k_force_dpd<false, true>, g, b, s, e0, e1, d, f_out, so);
+      else launch_k(k_force_dpd<false, false>, g, b, s, e0, e1, d, f_out, so);
+    }
+  } else if (mixed) {
     if (bonds) launch_k(k_force<MODE, true, true, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
     else launch_k(k_force<MODE, true, false, SAMPLE, STAGED>, g, b, s, e0, e1, d, f_out, so);
   } else {
