@@ -611,11 +611,12 @@ def main():
         kskin = skin if kg else pick_skin("kg", 0.01, "fp64")[0]
         extra["c5_mixed_batched_kg_sweep"] = guarded(
             "c5 sweep", lambda: c5_sweep(scale=args.c5_scale, steps=args.c5_steps))
-        # dt 0.01 at shear rate 0.01; at 0.1 the melt can stretch a bond to R0
-        # within 2e4 steps of dt 0.01 (a latched LE_E_BOND), so that run takes 0.005
-        for sr3, dt3 in ((0.01, None), (0.1, 0.005)):
+        # 200 time units each: dt 0.01 at shear rate 0.01; at 0.1 the melt can
+        # stretch a bond to R0 within 2e4 steps of dt 0.01 (a latched LE_E_BOND),
+        # so that run takes 4e4 steps of dt 0.005
+        for sr3, dt3, n3 in ((0.01, None, 20000), (0.1, 0.005, 40000)):
             viscosity[f"kg_400k_shear_rate_{sr3}"] = guarded(
-                "kg viscosity", lambda: viscosity_pair("kg", sr3, kskin, steps=20000, warmup=1000, dt=dt3))
+                "kg viscosity", lambda: viscosity_pair("kg", sr3, kskin, steps=n3, warmup=1000, dt=dt3))
     if args.serve and not args.no_extra and th == "langevin":
         extra["serving"] = guarded("serving", lambda: serving_bench(args.serve_requests))
 
