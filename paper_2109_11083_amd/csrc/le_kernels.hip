@@ -908,6 +908,39 @@ __device__ __forceinline__ void neighbors_body(const Dev& d, const int tile) {
       }
     }
   }
+  {
+    // the second sub-list's last, partial block (still in its thread's ring)
+    // moves to the end of the first: the two sub-lists then carry one padding
+    // instead of two (the force kernels read them as one sequence).  Entries
+    // of the halo layout's rows beyond the halo went straight to global
+    // memory and stay where they are.
+    // entries of the partial block | its ring half << 8, where the staged y
+    // coordinates were (every wave has left the scan after this barrier)
+    int* tail = reinterpret_cast<int*>(hy);
+    __syncthreads();
+    if (half == 1)
+      tail[tl] = GL ? (nog & (kOtherBatch - 1)) : ((npl & (kPlainBatch - 1)) | (((npl >> 3) & 1) << 8));
+    __syncthreads();
+    const int r = tail[tl] & 0xff;
+    const int pt = (int)threadIdx.x + kTile;  // the particle's second thread
+    if (half == 0) {
+      if constexpr (GL) {
+        for (int k = 0; k < r; ++k) og_append(gslot[pt][k]);
+      } else {
+        const int src = (tail[tl] >> 8) * 8;
+        for (int k = 0; k < r; ++k) {
+          lbuf[threadIdx.x][npl & 15] = lbuf[pt][src + k];
+          ++npl;
+          const int blk = (npl >> 3) - 1;  // completed by this entry
+          if ((npl & 7) == 0 && (blk + 1) * 8 <= K)
+            reinterpret_cast<uint4*>(d.nl16)[(size_t)blk * np2 + v] =
+                *reinterpret_cast<const uint4*>(&lbuf[threadIdx.x][(blk & 1) * 8]);
+        }
+      }
+    } else {
+      if constexpr (GL) nog -= r; else npl -= r;
+    }
+  }
   {  // telemetry (entries per particle, both sub-lists): one atomic per block
     __shared__ int wmax[2 * kTile / 64];
     // the counts of the second halves go where the staged x coordinates
