@@ -138,7 +138,8 @@ typedef struct le_params {
   int32_t precision;   /* LE_FP64 or LE_MIXED                                       */
   int32_t cells[3];    /* cell grid; 0 = floor(L_a / (rc + skin)); each must be >= 3 */
   int32_t max_neighbors; /* neighbour-list capacity per particle (two sub-lists of half
-                            each); 0 = from density */
+                            each; the first also takes the second's partial last block
+                            of up to 7 entries); 0 = from density */
   int32_t tune;        /* pair-kernel layout: 0 = chosen from density, 1 = partners staged
                           in an LDS halo per tile, 2 = partners read from global memory;
                           the physics is the same (sums may differ in the last bits) */

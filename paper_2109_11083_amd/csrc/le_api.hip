@@ -102,7 +102,8 @@ le_status validate(const le_params* p, Geometry* g) {
   g->rc = rc;
   g->rlist = rlist;
   // capacity of each of a particle's two sub-lists (each holds about half of
-  // its partners): max_neighbors / 2, or from the density with a margin
+  // its partners; the first also the second's partial last block):
+  // max_neighbors / 2, or from the density with a margin
   if (p->max_neighbors > 0) {
     g->K = (p->max_neighbors + 1) / 2;
   } else {
